@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark of the Hough-transform fill + peak search on one MI355X.
+
+One step = one event of the paper-shaped workload (5000 hits, 4 theta x 16 phi x 1024 A x 1024 B
+uint32 vote matrix, threshold 9) through the whole path: per-hit prep and bucketing, the fill
+(which writes every cell of the 256 MiB matrix), the peak search, and the return of the peak
+list to pinned host memory. Inputs are resident in HBM when the timed region starts. Prints one
+JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "events/s + Gvotes/s on 1 MI355X; p50/p99 event latency, served vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def cpu_baseline(spec, workload, seconds):
+    """The oracle, single-threaded, on a bounded sample of the same workload."""
+    from oracle import oracle
+    from paper_1507_03074_amd import synth
+    g = oracle.OracleGrid(*spec.as_tuple())
+    done, votes, t0 = 0, [], time.perf_counter()
+    buf = np.empty(spec.shape, np.uint32)
+    while done < 3 or (time.perf_counter() - t0 < seconds and done < 100):
+        ev = synth.make_event(workload, 1000 + done)
+        ts = time.perf_counter()
+        M, v = oracle.fill(g, ev.x, ev.y, ev.z, out=buf)
+        oracle.peaks(g, M)
+        votes.append((time.perf_counter() - ts, v, ev))
+        done += 1
+    t_total = sum(t for t, _, _ in votes)
+    return dict(value=done / t_total, unit="events/s", cores=1, kind="oracle",
+                sample="%d events of workload 1 (5000 hits, 4x16x1024x1024), fill + peaks, "
+                       "one thread, %.1f s" % (done, t_total)), votes
+
+
+def measure_peaks(B, torch, acc_bytes):
+    """Ceilings measured in the same run (one launch each, timed with events on this stream)."""
+    stream = torch.cuda.current_stream()
+    buf = torch.empty(acc_bytes // 4, dtype=torch.int32, device="cuda")
+    buf2 = torch.empty_like(buf)
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+    L = B.lib()
+    sp = ctypes_stream(stream)
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3 / reps
+
+    nbytes = buf.numel() * 4
+    t_wm = [timed(lambda m=m: L.ht_bench_hbm_write(buf.data_ptr(), nbytes, m, sp)) for m in (0, 1, 2)]
+    t_w = min(t_wm)
+    t_r = timed(lambda: L.ht_bench_hbm_read(buf.data_ptr(), nbytes, sink.data_ptr(), sp))
+    t_c = timed(lambda: L.ht_bench_copy(buf2.data_ptr(), buf.data_ptr(), nbytes, sp))
+    n_ops = 1 << 28
+    t_a = timed(lambda: L.ht_bench_atomic_rand(buf.data_ptr(), buf.numel(), n_ops, sp), reps=3)
+    small = 1 << 20  # 4 MiB: an L2-resident target
+    t_al = timed(lambda: L.ht_bench_atomic_rand(buf.data_ptr(), small, n_ops, sp), reps=3)
+    blocks, iters = 256 * 16, 4096
+    t_l = timed(lambda: L.ht_bench_lds_atomic(blocks, iters, sink.data_ptr(), sp), reps=3)
+    del buf, buf2
+    return {"hbm_write_GBs": round(nbytes / t_w / 1e9, 1),
+            "hbm_write_GBs_by_mode": {"nontemporal16": round(nbytes / t_wm[0] / 1e9, 1),
+                                      "store16": round(nbytes / t_wm[1] / 1e9, 1),
+                                      "store4": round(nbytes / t_wm[2] / 1e9, 1)},
+            "hbm_read_GBs": round(nbytes / t_r / 1e9, 1),
+            "copy_GBs": round(2 * nbytes / t_c / 1e9, 1),
+            "atomic_rand_Gops": round(n_ops / t_a / 1e9, 2),
+            "atomic_l2_Gops": round(n_ops / t_al / 1e9, 2),
+            "lds_atomic_Gops": round(blocks * 256 * iters / t_l / 1e9, 1),
+            "buffer_MiB": nbytes >> 20}
+
+
+def ctypes_stream(stream):
+    import ctypes
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--events", type=int, default=16, help="distinct resident events cycled")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="main line only (no extra workloads)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(events shard across GPUs with no collective; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1507_03074_amd import binding as B
+    from paper_1507_03074_amd import synth
+
+    if not os.path.exists(B.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    torch.cuda.set_device(0)
+    workload = 1
+    spec = synth.WORKLOADS[workload].grid
+    cap = 4096
+    log("generating %d events of workload %d" % (args.events, workload))
+    evs = [synth.make_event(workload, e) for e in range(args.events)]
+    dev_hits = [B.hits_to_device(e.x, e.y, e.z) for e in evs]
+    acc = B.new_acc(spec)
+    out = torch.empty((args.events, cap, 2), dtype=torch.int32, device="cuda")
+    nf = torch.zeros(args.events, dtype=torch.int64, device="cuda")
+    h_out = torch.empty((args.events, cap, 2), dtype=torch.int32, pin_memory=True)
+    h_nf = torch.zeros(args.events, dtype=torch.int64, pin_memory=True)
+    stream = torch.cuda.current_stream()
+
+    def step(k):
+        i = k % args.events
+        x, y, z = dev_hits[i]
+        B.ht_fill_peaks(spec, x, y, z, acc, out[i], cap, nf[i:i + 1], stream)
+        h_nf[i:i + 1].copy_(nf[i:i + 1], non_blocking=True)
+        h_out[i].copy_(out[i], non_blocking=True)
+
+    # votes per event (the matrix sum; equal to the oracle's count by the parity tests)
+    votes = []
+    for i in range(args.events):
+        x, y, z = dev_hits[i]
+        B.ht_fill(spec, x, y, z, acc)
+        votes.append(int(acc.sum(dtype=torch.int64).item()))
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+
+    # timed region; the library records HIP events around its stages on `stream`
+    B.ht_profile_read("fill", reset=True)
+    B.ht_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.ht_profile_enable(False)
+    fill_ms, fill_n = B.ht_profile_read("fill")
+    prep_ms, prep_n = B.ht_profile_read("prep")
+    peak_ms, peak_n = B.ht_profile_read("peaks", reset=True)
+    elapsed = t1 - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    ev_per_s = args.steps / elapsed
+    total_votes = sum(votes[k % args.events] for k in range(args.steps))
+    # peak lists returned in the timed region agree with a fresh run (sanity, not parity)
+    nfound = h_nf.numpy().copy()
+
+    # the same timed loop without the stage events, for the overhead of the timers themselves
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+
+    cells = spec.n_cells
+    t = B.ht_tiling(spec)
+    # (hit, cell) records per event: the fill reads each bucketed record (16 B)
+    entries = []
+    for x, y, z in dev_hits:
+        info, _, _ = B.ht_debug_hit_values(spec, x, y, z)
+        entries.append(int(info[:, 3].sum().item()))
+    fill_avg_s = fill_ms / 1000.0 / max(fill_n, 1)
+    # algorithmic bytes of one fill launch: the matrix written once (4 B per cell) plus each
+    # bucketed (hit, cell) record read once (16 B)
+    hit_entries = float(np.mean(entries))
+    alg_bytes = 4.0 * cells + 16.0 * hit_entries
+    achieved = alg_bytes / fill_avg_s / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(ev_per_s, 2),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": synth.WORKLOADS[workload].name, "hits_per_event": 5000,
+                   "grid": list(spec.shape), "threshold": spec.threshold,
+                   "path": "ht_fill_peaks (fused) + peak list D2H", "tile_rows": t["rows"],
+                   "resident_events": args.events},
+        "gvotes_per_s": round(total_votes / elapsed / 1e9, 3),
+        "votes_per_event": round(float(np.mean(votes)), 1),
+        "fill_gvotes_per_s": round(np.mean(votes) / fill_avg_s / 1e9, 3),
+        "stage_ms": {"prep": round(prep_ms / max(prep_n, 1), 4),
+                     "fill": round(fill_avg_s * 1e3, 4),
+                     "peaks": round(peak_ms / max(peak_n, 1), 4)},
+        "ms_per_step_without_stage_events": round(1000.0 * (t3 - t2) / args.steps, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_fill", "alg_bytes_per_launch": alg_bytes},
+        "peaks_per_event": round(float(np.mean(nfound)), 1),
+    }
+    # the plain baseline: zero the matrix, one global atomicAdd per vote (paper-style kernel)
+    torch.cuda.synchronize()
+    B.ht_profile_read("fill_atomic", reset=True)
+    B.ht_profile_enable(True)
+    for k in range(min(args.steps, 50)):
+        x, y, z = dev_hits[k % args.events]
+        B.ht_fill(spec, x, y, z, acc, stream, atomic=True)
+    torch.cuda.synchronize()
+    B.ht_profile_enable(False)
+    fa_ms, fa_n = B.ht_profile_read("fill_atomic", reset=True)
+    fa_s = fa_ms / 1e3 / max(fa_n, 1)
+    line["plain_atomic_fill"] = {"ms": round(fa_s * 1e3, 4),
+                                 "gvotes_per_s": round(np.mean(votes) / fa_s / 1e9, 3)}
+    pk = measure_peaks(B, torch, 4 * cells)
+    line["measured_peaks"] = pk
+    line["fill_frac_of_measured_write"] = round(achieved / pk["hbm_write_GBs"], 4)
+    line["fill_votes_vs_atomic_roofline"] = round(
+        line["fill_gvotes_per_s"] / pk["atomic_rand_Gops"], 3)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cb, _ = cpu_baseline(spec, workload, args.cpu_seconds)
+        line["cpu_baseline"] = cb
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,654 @@
+// ht_api.cpp -- C ABI of libht.so: validation, bin-rule tables, tiling, scratch, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "ht_debug.h"
+#include "ht_internal.h"
+
+namespace ht {
+hipError_t launch_debug_hits(const DevGrid& g, const float* x, const float* y, const float* z,
+                             int64_t n, int32_t* info, float* vals, int32_t* slabs, hipStream_t s);
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what)
+{
+  return fail(e == hipErrorOutOfMemory ? HT_ENOMEM : HT_EDEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+static const double kPi = 3.14159265358979323846;
+
+int validate_grid(const ht_grid* g)
+{
+  if (!g) return fail(HT_EINVAL, "grid is NULL");
+  if (g->n_theta < 1 || g->n_phi < 3 || g->n_a < 1 || g->n_b < 1)
+    return fail(HT_EINVAL, "grid needs n_theta >= 1, n_phi >= 3, n_a >= 1, n_b >= 1");
+  if (g->n_a > (1 << 24) || g->n_b > (1 << 24)) return fail(HT_EINVAL, "n_a and n_b must be <= 2^24");
+  if ((int64_t)g->n_theta * g->n_phi > kMaxSlabs) return fail(HT_EINVAL, "n_theta*n_phi must be <= 4096");
+  if (!std::isfinite(g->a_min) || !std::isfinite(g->a_max) || !std::isfinite(g->b_min) ||
+      !std::isfinite(g->b_max))
+    return fail(HT_EINVAL, "grid ranges must be finite");
+  if (!(g->a_min < g->a_max) || !(g->b_min < g->b_max))
+    return fail(HT_EINVAL, "grid ranges need min < max");
+  if (g->threshold < 1) return fail(HT_EINVAL, "threshold must be >= 1");
+  const double cells = (double)g->n_theta * g->n_phi * (double)g->n_a * (double)g->n_b;
+  if (cells > 4294967296.0) return fail(HT_EINVAL, "more than 2^32 cells");
+  return HT_OK;
+}
+
+uint64_t n_cells(const ht_grid& g) { return (uint64_t)g.n_theta * g.n_phi * g.n_a * g.n_b; }
+
+// Bin-rule tables, computed in double and rounded once to float.
+void host_tables(const ht_grid& g, std::vector<float>& a2, float& inv_db, std::vector<float>& phi,
+                 std::vector<float>& th)
+{
+  a2.resize(g.n_a);
+  const double da = ((double)g.a_max - (double)g.a_min) / (double)g.n_a;
+  for (int32_t i = 0; i < g.n_a; ++i)
+    a2[i] = (float)(2.0 * (double)g.a_min + (double)(2 * (int64_t)i + 1) * da);
+  inv_db = (float)((double)g.n_b / ((double)g.b_max - (double)g.b_min));
+  phi.resize(4 * (size_t)g.n_phi);
+  for (int32_t m = 0; m < 2 * g.n_phi; ++m) {
+    const double ang = ((double)m * kPi) / (double)g.n_phi;
+    phi[2 * m] = (float)std::cos(ang);
+    phi[2 * m + 1] = (float)std::sin(ang);
+  }
+  th.resize(2 * (2 * (size_t)g.n_theta + 1));
+  for (int32_t m = 0; m <= 2 * g.n_theta; ++m) {
+    const double ang = ((double)m * kPi) / (double)(2 * g.n_theta);
+    th[2 * m] = (float)std::cos(ang);
+    th[2 * m + 1] = (float)std::sin(ang);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Tiling
+// ---------------------------------------------------------------------------------------------
+struct Tiling {
+  int32_t rows, tiles_per_slab, n_tiles, cand_cap, lds_fill, group_tiles, nt_store;
+};
+
+static int env_int(const char* name, int def)
+{
+  const char* v = std::getenv(name);
+  return v && *v ? std::atoi(v) : def;
+}
+
+// Largest power-of-two row count (<= 64) whose u32 tile fits the LDS budget; the candidate
+// slots per tile scale with the tile (1/32 of its cells, 64..1024).
+Tiling choose_tiling(const ht_grid& g)
+{
+  Tiling t;
+  const int64_t row_bytes = (int64_t)g.n_b * 4;
+  const int64_t budget = env_int("HT_FILL_LDS_BYTES", 32768);
+  const int64_t lds_max = 65536 - 8192;  // room for the candidate list
+  t.lds_fill = row_bytes <= lds_max ? 1 : 0;
+  int rows = 1;
+  if (t.lds_fill) {
+    while (rows < 64 && (int64_t)(rows * 2) * row_bytes <= std::max<int64_t>(budget, row_bytes) &&
+           rows < g.n_a)
+      rows *= 2;
+    const int forced = env_int("HT_FILL_ROWS", 0);
+    if (forced > 0 && (forced & (forced - 1)) == 0 && forced <= 64 &&
+        (int64_t)forced * row_bytes <= lds_max)
+      rows = forced;
+  }
+  // keep the tile count inside a 32-bit grid dimension
+  while (rows < 64 && (int64_t)g.n_theta * g.n_phi * ((g.n_a + rows - 1) / rows) > 0x7fffffffLL) rows *= 2;
+  t.rows = rows;
+  t.tiles_per_slab = (g.n_a + rows - 1) / rows;
+  t.n_tiles = g.n_theta * g.n_phi * t.tiles_per_slab;
+  const int64_t tile_cells = (int64_t)rows * g.n_b;
+  int cap = 64;
+  while (cap < 1024 && cap * 32 < tile_cells) cap *= 2;
+  const int forced_cap = env_int("HT_CAND_CAP", 0);
+  if (forced_cap >= 2 && forced_cap <= 4096 && (forced_cap & (forced_cap - 1)) == 0) cap = forced_cap;
+  t.cand_cap = cap;
+  // peak-search groups: small groups spread clustered candidates over more workgroups; the
+  // write kernel sums the earlier groups' totals, so keep the group count moderate
+  int gt = 16;
+  while (gt < 64 && ((int64_t)t.n_tiles + gt - 1) / gt > 2048) gt *= 2;
+  const int forced_gt = env_int("HT_GROUP_TILES", 0);
+  if (forced_gt == 16 || forced_gt == 32 || forced_gt == 64) gt = forced_gt;
+  t.group_tiles = gt;
+  t.nt_store = env_int("HT_FILL_NT", 0) ? 1 : 0;
+  return t;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Device tables, cached per (device, grid)
+// ---------------------------------------------------------------------------------------------
+struct DevTables {
+  float* a2 = nullptr;
+  float* phi = nullptr;
+  float* th = nullptr;
+  float inv_db = 0.0f;
+};
+
+static std::mutex g_mu;
+typedef std::tuple<int, int32_t, int32_t, int32_t, int32_t, uint32_t, uint32_t, uint32_t, uint32_t>
+    TabKey;
+static std::map<TabKey, DevTables> g_tables;
+
+static uint32_t fbits(float f)
+{
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+
+int get_tables(const ht_grid& g, int dev, DevTables* out)
+{
+  TabKey key{dev, g.n_theta, g.n_phi, g.n_a, g.n_b, fbits(g.a_min), fbits(g.a_max), fbits(g.b_min),
+             fbits(g.b_max)};
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_tables.find(key);
+  if (it != g_tables.end()) {
+    *out = it->second;
+    return HT_OK;
+  }
+  std::vector<float> a2, phi, th;
+  DevTables t;
+  host_tables(g, a2, t.inv_db, phi, th);
+  hipError_t e;
+  if ((e = hipMalloc(&t.a2, a2.size() * 4)) != hipSuccess) return fail_hip(e, "hipMalloc(tables)");
+  if ((e = hipMalloc(&t.phi, phi.size() * 4)) != hipSuccess) return fail_hip(e, "hipMalloc(tables)");
+  if ((e = hipMalloc(&t.th, th.size() * 4)) != hipSuccess) return fail_hip(e, "hipMalloc(tables)");
+  if ((e = hipMemcpy(t.a2, a2.data(), a2.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(t.phi, phi.data(), phi.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(t.th, th.data(), th.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail_hip(e, "hipMemcpy(tables)");
+  g_tables[key] = t;
+  *out = t;
+  return HT_OK;
+}
+
+DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
+{
+  DevGrid d;
+  d.n_theta = g.n_theta;
+  d.n_phi = g.n_phi;
+  d.n_a = g.n_a;
+  d.n_b = g.n_b;
+  d.b_min = g.b_min;
+  d.inv_db = t.inv_db;
+  d.nb_f = (float)g.n_b;
+  d.threshold = g.threshold;
+  d.n_slabs = g.n_theta * g.n_phi;
+  d.rows = tl.rows;
+  d.tiles_per_slab = tl.tiles_per_slab;
+  d.n_tiles = tl.n_tiles;
+  d.cand_cap = tl.cand_cap;
+  d.lds_fill = tl.lds_fill;
+  d.group_tiles = tl.group_tiles;
+  d.nt_store = tl.nt_store;
+  d.a2 = t.a2;
+  d.phi_cs = t.phi;
+  d.th_cs = t.th;
+  return d;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per-event scratch
+// ---------------------------------------------------------------------------------------------
+static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t event_scratch_bytes(const DevGrid& g, int64_t n)
+{
+  const size_t nn = (size_t)std::max<int64_t>(n, 0);
+  size_t b = 0;
+  b += al(4 * ((size_t)g.n_slabs + 1));       // slab_off
+  b += al(16 * nn);                           // hit_slab
+  b += al(16 * nn);                           // hit_pos
+  b += al(16 * nn);                           // hit_rec
+  b += al(64 * nn);                           // list
+  b += al(4 * (size_t)g.n_tiles);             // tile_cnt
+  b += al(8 * (size_t)g.n_tiles * g.cand_cap);  // cand
+  b += al(4 * (size_t)g.n_tiles);             // tile_pk
+  b += al(4 * (size_t)n_groups(g));           // group_pk
+  return b;
+}
+
+void carve_event_scratch(const DevGrid& g, int64_t n, char* p, EvDesc* ev)
+{
+  const size_t nn = (size_t)std::max<int64_t>(n, 0);
+  auto take = [&p](size_t bytes) {
+    char* r = p;
+    p += al(bytes);
+    return r;
+  };
+  ev->slab_off = (uint32_t*)take(4 * ((size_t)g.n_slabs + 1));
+  ev->hit_slab = (int32_t*)take(16 * nn);
+  ev->hit_pos = (uint32_t*)take(16 * nn);
+  ev->hit_rec = (float4*)take(16 * nn);
+  ev->list = (float4*)take(64 * nn);
+  ev->tile_cnt = (uint32_t*)take(4 * (size_t)g.n_tiles);
+  ev->cand = (uint2*)take(8 * (size_t)g.n_tiles * g.cand_cap);
+  ev->tile_pk = (uint32_t*)take(4 * (size_t)g.n_tiles);
+  ev->group_pk = (uint32_t*)take(4 * (size_t)n_groups(g));
+}
+
+// Scratch owned by the library, one per (device, stream). Calls on one stream are ordered on
+// the device, so they may reuse the same scratch; growing it waits for the stream first.
+struct Workspace {
+  char* dev = nullptr;
+  size_t bytes = 0;
+  uint32_t* ctr = nullptr;  // zeroed slab counters, kCounterBytes per event
+  int ctr_events = 0;
+  EvDesc* h_ev = nullptr;   // pinned staging of batch descriptors
+  EvDesc* d_ev = nullptr;
+  int ev_cap = 0;
+  hipEvent_t ev_copied = nullptr;
+};
+
+static std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+
+int get_workspace(int dev, hipStream_t s, size_t bytes, Workspace** out)
+{
+  Workspace* w;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace*& slot = g_ws[{dev, s}];
+    if (!slot) slot = new Workspace();
+    w = slot;
+  }
+  if (bytes > w->bytes) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    if (w->dev) (void)hipFree(w->dev);
+    w->dev = nullptr;
+    w->bytes = 0;
+    const size_t want = std::max(bytes, (size_t)1 << 20);
+    if ((e = hipMalloc(&w->dev, want)) != hipSuccess) return fail_hip(e, "hipMalloc(scratch)");
+    w->bytes = want;
+  }
+  *out = w;
+  return HT_OK;
+}
+
+int ensure_counters(Workspace* w, int n_ev, hipStream_t s)
+{
+  if (n_ev <= w->ctr_events) return HT_OK;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  if (w->ctr) (void)hipFree(w->ctr);
+  w->ctr = nullptr;
+  w->ctr_events = 0;
+  const int want = std::max(n_ev, 16);
+  if ((e = hipMalloc((void**)&w->ctr, kCounterBytes * want)) != hipSuccess)
+    return fail_hip(e, "hipMalloc(counters)");
+  if ((e = hipMemset(w->ctr, 0, kCounterBytes * want)) != hipSuccess) return fail_hip(e, "hipMemset(counters)");
+  w->ctr_events = want;
+  return HT_OK;
+}
+
+uint32_t* counters_of(Workspace* w, int i) { return w->ctr + (size_t)i * (kCounterBytes / 4); }
+
+int ensure_ev_staging(Workspace* w, int n_ev, hipStream_t s)
+{
+  if (n_ev <= w->ev_cap) {
+    if (w->ev_copied) {
+      hipError_t e = hipEventSynchronize(w->ev_copied);
+      if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+    }
+    return HT_OK;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  if (w->h_ev) (void)hipHostFree(w->h_ev);
+  if (w->d_ev) (void)hipFree(w->d_ev);
+  w->h_ev = nullptr;
+  w->d_ev = nullptr;
+  w->ev_cap = 0;
+  int cap = std::max(n_ev, 16);
+  if ((e = hipHostMalloc((void**)&w->h_ev, sizeof(EvDesc) * cap, hipHostMallocDefault)) != hipSuccess)
+    return fail_hip(e, "hipHostMalloc(descriptors)");
+  if ((e = hipMalloc((void**)&w->d_ev, sizeof(EvDesc) * cap)) != hipSuccess)
+    return fail_hip(e, "hipMalloc(descriptors)");
+  if (!w->ev_copied && (e = hipEventCreateWithFlags(&w->ev_copied, hipEventDisableTiming)) != hipSuccess)
+    return fail_hip(e, "hipEventCreate");
+  w->ev_cap = cap;
+  return HT_OK;
+}
+
+int make_device_grid(const ht_grid& g, int dev, DevGrid* out)
+{
+  int rc = validate_grid(&g);
+  if (rc) return rc;
+  DevTables t;
+  if ((rc = get_tables(g, dev, &t))) return rc;
+  *out = make_devgrid(g, t, choose_tiling(g));
+  return HT_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stage profiler: HIP events recorded on the launch stream around each stage.
+// ---------------------------------------------------------------------------------------------
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_prof_pool;
+
+static hipEvent_t prof_event()
+{
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct StageTimer {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  StageTimer(const char* n, hipStream_t st) : name(n), s(st)
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    a = prof_event();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~StageTimer()
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!a) return;
+    hipEvent_t b = prof_event();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    g_prof.push_back({name, a, b});
+  }
+};
+
+struct Prepared {
+  DevGrid g;
+  int dev;
+  hipStream_t s;
+};
+
+int prepare(const ht_grid* grid, void* stream, Prepared* p)
+{
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  hipError_t e = hipGetDevice(&p->dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  if ((rc = make_device_grid(*grid, p->dev, &p->g))) return rc;
+  p->s = (hipStream_t)stream;
+  return HT_OK;
+}
+
+int check_launch(hipError_t e, const char* what)
+{
+  if (e != hipSuccess) return fail_hip(e, what);
+  return HT_OK;
+}
+
+int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, hipStream_t s)
+{
+  EvDesc none;
+  std::memset(&none, 0, sizeof(none));
+  int rc;
+  {
+    StageTimer t("prep", s);
+    if ((rc = check_launch(launch_prep(g, none, d_ev, n_ev, max_hits, s), "prep launch"))) return rc;
+  }
+  if (g.lds_fill) {
+    StageTimer t("fill", s);
+    if ((rc = check_launch(launch_fill(g, none, d_ev, n_ev, true, s), "fill launch"))) return rc;
+  } else {
+    {
+      StageTimer t("fill_atomic", s);
+      if ((rc = check_launch(launch_fill_atomic(g, none, d_ev, n_ev, max_hits, s), "fill launch")))
+        return rc;
+    }
+    StageTimer t("candidates", s);
+    if ((rc = check_launch(launch_candidates(g, none, d_ev, n_ev, s), "candidate launch"))) return rc;
+  }
+  StageTimer t("peaks", s);
+  return check_launch(launch_peaks(g, none, d_ev, n_ev, s), "peak launch");
+}
+
+int run_event(const ht_grid* grid, const float* x, const float* y, const float* z, int64_t n,
+              uint32_t* acc, ht_peak* out, int64_t cap, int64_t* n_found, void* stream,
+              bool do_fill, bool do_peaks, bool force_atomic)
+{
+  if (n < 0) return fail(HT_EINVAL, "n_hits < 0");
+  if (!acc) return fail(HT_EINVAL, "acc is NULL");
+  if (do_fill && n > 0 && (!x || !y || !z)) return fail(HT_EINVAL, "hit arrays are NULL");
+  if (do_peaks && (cap < 0 || !n_found || (cap > 0 && !out)))
+    return fail(HT_EINVAL, "peak output arguments are invalid");
+  if (n > ((int64_t)1 << 28)) return fail(HT_EINVAL, "n_hits must be <= 2^28");
+  Prepared p;
+  int rc = prepare(grid, stream, &p);
+  if (rc) return rc;
+  const int64_t nh = do_fill ? n : 0;
+  Workspace* w;
+  if ((rc = get_workspace(p.dev, p.s, event_scratch_bytes(p.g, nh), &w))) return rc;
+  if ((rc = ensure_counters(w, 1, p.s))) return rc;
+  EvDesc ev;
+  std::memset(&ev, 0, sizeof(ev));
+  carve_event_scratch(p.g, nh, w->dev, &ev);
+  ev.slab_cnt = counters_of(w, 0);
+  ev.x = x;
+  ev.y = y;
+  ev.z = z;
+  ev.n_hits = nh;
+  ev.acc = acc;
+  ev.out = out;
+  ev.cap = cap;
+  ev.n_found = n_found;
+  const bool atomic = force_atomic || !p.g.lds_fill;
+  if (do_fill) {
+    {
+      StageTimer t("prep", p.s);
+      if ((rc = check_launch(launch_prep(p.g, ev, nullptr, 1, nh, p.s), "prep launch"))) return rc;
+    }
+    if (atomic) {
+      StageTimer t("fill_atomic", p.s);
+      if ((rc = check_launch(launch_fill_atomic(p.g, ev, nullptr, 1, nh, p.s), "fill launch"))) return rc;
+    } else {
+      StageTimer t("fill", p.s);
+      if ((rc = check_launch(launch_fill(p.g, ev, nullptr, 1, do_peaks, p.s), "fill launch"))) return rc;
+    }
+  }
+  if (do_peaks) {
+    if (!do_fill || atomic) {
+      StageTimer t("candidates", p.s);
+      if ((rc = check_launch(launch_candidates(p.g, ev, nullptr, 1, p.s), "candidate launch"))) return rc;
+    }
+    StageTimer t("peaks", p.s);
+    if ((rc = check_launch(launch_peaks(p.g, ev, nullptr, 1, p.s), "peak launch"))) return rc;
+  }
+  return HT_OK;
+}
+
+}  // namespace ht
+
+using namespace ht;
+
+extern "C" {
+
+int ht_tables(const ht_grid* grid, float* a2, float* inv_db, float* phi_cs, float* th_cs)
+{
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (!a2 || !inv_db || !phi_cs || !th_cs) return fail(HT_EINVAL, "table pointers are NULL");
+  std::vector<float> va2, vphi, vth;
+  float inv;
+  host_tables(*grid, va2, inv, vphi, vth);
+  std::memcpy(a2, va2.data(), va2.size() * 4);
+  *inv_db = inv;
+  std::memcpy(phi_cs, vphi.data(), vphi.size() * 4);
+  std::memcpy(th_cs, vth.data(), vth.size() * 4);
+  return HT_OK;
+}
+
+int ht_tiling(const ht_grid* grid, int32_t* rows, int32_t* n_tiles, int32_t* cand_cap,
+              int32_t* lds_fill)
+{
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  Tiling t = choose_tiling(*grid);
+  if (rows) *rows = t.rows;
+  if (n_tiles) *n_tiles = t.n_tiles;
+  if (cand_cap) *cand_cap = t.cand_cap;
+  if (lds_fill) *lds_fill = t.lds_fill;
+  return HT_OK;
+}
+
+int ht_fill(const ht_grid* grid, const float* x, const float* y, const float* z, int64_t n_hits,
+            uint32_t* acc, void* stream)
+{
+  return run_event(grid, x, y, z, n_hits, acc, nullptr, 0, nullptr, stream, true, false, false);
+}
+
+int ht_fill_atomic(const ht_grid* grid, const float* x, const float* y, const float* z,
+                   int64_t n_hits, uint32_t* acc, void* stream)
+{
+  return run_event(grid, x, y, z, n_hits, acc, nullptr, 0, nullptr, stream, true, false, true);
+}
+
+int ht_peaks(const ht_grid* grid, const uint32_t* acc, ht_peak* out, int64_t capacity,
+             int64_t* n_found, void* stream)
+{
+  return run_event(grid, nullptr, nullptr, nullptr, 0, const_cast<uint32_t*>(acc), out, capacity,
+                   n_found, stream, false, true, false);
+}
+
+int ht_fill_peaks(const ht_grid* grid, const float* x, const float* y, const float* z,
+                  int64_t n_hits, uint32_t* acc, ht_peak* out, int64_t capacity,
+                  int64_t* n_found, void* stream)
+{
+  return run_event(grid, x, y, z, n_hits, acc, out, capacity, n_found, stream, true, true, false);
+}
+
+int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_events,
+                        const float* x, const float* y, const float* z, uint32_t* acc,
+                        ht_peak* out, int64_t* n_found, void* stream)
+{
+  if (n_events < 0 || n_events > 65535) return fail(HT_EINVAL, "n_events must be in [0, 65535]");
+  if (n_events == 0) return HT_OK;
+  if (!events || !acc || !n_found) return fail(HT_EINVAL, "NULL batch argument");
+  int64_t max_hits = 0, total_scratch = 0;
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  for (int32_t i = 0; i < n_events; ++i) {
+    const ht_event& ev = events[i];
+    if (ev.n_hits < 0 || ev.n_hits > ((int64_t)1 << 28) || ev.hit_offset < 0 || ev.peak_capacity < 0 ||
+        ev.peak_offset < 0)
+      return fail(HT_EINVAL, "event %d has invalid offsets or sizes", i);
+    if (ev.n_hits > 0 && (!x || !y || !z)) return fail(HT_EINVAL, "hit arrays are NULL");
+    if (ev.peak_capacity > 0 && !out) return fail(HT_EINVAL, "out is NULL");
+  }
+  Prepared p;
+  if ((rc = prepare(grid, stream, &p))) return rc;
+  std::vector<size_t> offs(n_events);
+  for (int32_t i = 0; i < n_events; ++i) {
+    max_hits = std::max(max_hits, events[i].n_hits);
+    offs[i] = (size_t)total_scratch;
+    total_scratch += (int64_t)event_scratch_bytes(p.g, events[i].n_hits);
+  }
+  Workspace* w;
+  if ((rc = get_workspace(p.dev, p.s, (size_t)total_scratch, &w))) return rc;
+  if ((rc = ensure_ev_staging(w, n_events, p.s))) return rc;
+  if ((rc = ensure_counters(w, n_events, p.s))) return rc;
+  const uint64_t cells = n_cells(*grid);
+  for (int32_t i = 0; i < n_events; ++i) {
+    const ht_event& ev = events[i];
+    EvDesc& d = w->h_ev[i];
+    std::memset(&d, 0, sizeof(d));
+    carve_event_scratch(p.g, ev.n_hits, w->dev + offs[i], &d);
+    d.slab_cnt = counters_of(w, i);
+    d.x = x ? x + ev.hit_offset : nullptr;
+    d.y = y ? y + ev.hit_offset : nullptr;
+    d.z = z ? z + ev.hit_offset : nullptr;
+    d.n_hits = ev.n_hits;
+    d.acc = acc + (size_t)i * cells;
+    d.out = out ? out + ev.peak_offset : nullptr;
+    d.cap = ev.peak_capacity;
+    d.n_found = n_found + i;
+  }
+  hipError_t e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, p.s);
+  if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(descriptors)");
+  if ((e = hipEventRecord(w->ev_copied, p.s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
+  return launch_batch(p.g, w->d_ev, n_events, max_hits, p.s);
+}
+
+int ht_debug_hit_values(const ht_grid* grid, const float* x, const float* y, const float* z,
+                        int64_t n_hits, int32_t* info, float* vals, int32_t* slabs, void* stream)
+{
+  if (n_hits < 0) return fail(HT_EINVAL, "n_hits < 0");
+  if (n_hits > 0 && (!x || !y || !z || !info || !vals || !slabs)) return fail(HT_EINVAL, "NULL pointer");
+  Prepared p;
+  int rc = prepare(grid, stream, &p);
+  if (rc) return rc;
+  return check_launch(launch_debug_hits(p.g, x, y, z, n_hits, info, vals, slabs, p.s), "debug launch");
+}
+
+int ht_profile_enable(int on)
+{
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return HT_OK;
+}
+
+int ht_profile_read(const char* name, double* total_ms, int64_t* count, int reset)
+{
+  if (!name || !total_ms || !count) return fail(HT_EINVAL, "NULL profile argument");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double tot = 0.0;
+  int64_t n = 0;
+  for (const ProfRec& r : g_prof) {
+    if (std::strcmp(r.name, name) != 0) continue;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize(profile)");
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, r.a, r.b)) != hipSuccess) return fail_hip(e, "hipEventElapsedTime");
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *count = n;
+  if (reset) {
+    for (const ProfRec& r : g_prof) {
+      (void)hipEventSynchronize(r.b);
+      g_prof_pool.push_back(r.a);
+      g_prof_pool.push_back(r.b);
+    }
+    g_prof.clear();
+  }
+  return HT_OK;
+}
+
+const char* ht_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// ht_internal.h -- types shared by the translation units of libht.so (kernels, C ABI, server).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "ht.h"
+
+namespace ht {
+
+// Largest number of (theta, phi) cells (slabs); their counters live in LDS during the prep.
+constexpr int kMaxSlabs = 4096;
+// Bytes of the per-event slab counters. They must be zero before a fill and the fill leaves
+// them zero, so they live in memory of their own that is cleared once when allocated.
+constexpr size_t kCounterBytes = sizeof(uint32_t) * kMaxSlabs;
+
+// Grid constants and tables as the kernels see them (passed by value as a kernel argument).
+struct DevGrid {
+  int32_t n_theta, n_phi, n_a, n_b;
+  float b_min;
+  float inv_db;     // (float)(n_b / (b_max - b_min))
+  float nb_f;       // (float)n_b, exact because n_b <= 2^24
+  uint32_t threshold;
+  int32_t n_slabs;         // n_theta * n_phi: one (A, B) slab per (theta, phi) cell
+  int32_t rows;            // A rows per tile; a tile is rows x n_b contiguous cells of one slab
+  int32_t tiles_per_slab;  // ceil(n_a / rows)
+  int32_t n_tiles;         // n_slabs * tiles_per_slab
+  int32_t cand_cap;        // candidate slots per tile (power of two)
+  int32_t lds_fill;        // 1: fill through an LDS tile; 0: global atomics (very wide B rows)
+  int32_t group_tiles;     // tiles per workgroup of the peak search (16, 32 or 64)
+  int32_t nt_store;        // 1: the fill writes the matrix with non-temporal stores
+  const float* a2;         // device [n_a]
+  const float* phi_cs;     // device [2 * 2 n_phi] (cos, sin)
+  const float* th_cs;      // device [2 * (2 n_theta + 1)] (cos, sin)
+};
+
+// One event's inputs, outputs and scratch (device pointers).
+struct EvDesc {
+  const float* x;
+  const float* y;
+  const float* z;
+  int64_t n_hits;
+  uint32_t* acc;        // [cells]
+  ht_peak* out;         // [cap]
+  int64_t cap;
+  int64_t* n_found;     // [1]
+  // scratch
+  uint32_t* slab_cnt;   // [n_slabs] counters (dedicated memory, see kCounterBytes)
+  uint32_t* slab_off;   // [n_slabs + 1]
+  int32_t* hit_slab;    // [4 n_hits] slab of each (hit, cell) or -1
+  uint32_t* hit_pos;    // [4 n_hits] position of the (hit, cell) in its slab list
+  float4* hit_rec;      // [n_hits] (x, r2, k, 0)
+  float4* list;         // [4 n_hits] hit records bucketed by slab
+  uint32_t* tile_cnt;   // [n_tiles] candidates (cells >= threshold) per tile
+  uint2* cand;          // [n_tiles * cand_cap] (cell, votes) of the candidates, ascending per tile
+  uint32_t* tile_pk;    // [n_tiles] peaks per tile
+  uint32_t* group_pk;   // [n_groups] peaks per group of tiles
+};
+
+// Bytes of per-event scratch for a grid tiling and an event size, and the carving of it.
+size_t event_scratch_bytes(const DevGrid& g, int64_t n_hits);
+void carve_event_scratch(const DevGrid& g, int64_t n_hits, char* base, EvDesc* ev);
+
+// Kernel launchers (ht_kernels.hip). `evs` is a device array of n_ev descriptors, or nullptr
+// for a single event passed by value in `ev0`. `max_hits` bounds n_hits over the events.
+hipError_t launch_prep(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                       int64_t max_hits, hipStream_t s);
+hipError_t launch_fill(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                       bool emit_candidates, hipStream_t s);
+hipError_t launch_candidates(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                             hipStream_t s);
+hipError_t launch_peaks(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                        hipStream_t s);
+// Plain fill: zero the matrix, then one global atomicAdd per vote (reference path and the
+// fallback for B rows too wide for an LDS tile).
+hipError_t launch_fill_atomic(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                              int64_t max_hits, hipStream_t s);
+
+size_t fill_lds_bytes(const DevGrid& g);
+int n_groups(const DevGrid& g);
+
+// Host helpers (ht_api.cpp).
+int fail(int code, const char* fmt, ...);
+int fail_hip(hipError_t e, const char* what);
+int validate_grid(const ht_grid* g);
+uint64_t n_cells(const ht_grid& g);
+// Validates the grid, uploads its tables once per device and picks the tiling.
+int make_device_grid(const ht_grid& g, int dev, DevGrid* out);
+// The whole batched pipeline (prep, fill with candidates, peaks) for n_ev events whose
+// descriptors are already in device memory.
+int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, hipStream_t s);
+
+}  // namespace ht

@@ -1,0 +1,807 @@
+// ht_kernels.hip -- gfx950 kernels of the Hough-transform fill and peak search.
+//
+// Pipeline (paper section 2: every hit votes along its circles through the interaction point,
+// then the local maxima above a threshold are the track candidates). Every kernel takes a batch
+// of events (grid.y = event), so one launch per stage serves a single event or a whole batch:
+//   k_prep        per hit: validity, r2, k = 1/(2y), theta/phi half-sectors and the 2-4
+//                 (theta, phi) cells; the (hit, cell) records are counted per slab (one slab =
+//                 the A x B plane of one (theta, phi) cell) with LDS-aggregated atomics
+//   k_bucket      every workgroup scans the slab counts in LDS and scatters its hits' records
+//                 into per-slab lists (a counting sort)
+//   k_fill        one workgroup per (slab, tile of A rows): the slab's records vote into an LDS
+//                 tile (ds_add), then every cell of the tile is written to HBM once with
+//                 coalesced 16-byte stores (so the matrix needs no memset), and the cells >= threshold
+//                 are kept as sorted per-tile candidates (cell, votes)
+//   k_peak_mark   per group of 16-64 tiles: each candidate takes the strict 3^4 test against its
+//                 80 neighbours (a cell below the threshold can never beat a candidate, so only
+//                 candidates need testing); peaks are compacted in order per group
+//   k_peak_write  each group's output offset from the group totals; the ordered peak list
+// ht_peaks on an arbitrary matrix replaces prep and fill with k_cand_scan (one read of it).
+// No kernel synchronises workgroups with each other: on this multi-XCD part an agent-scope
+// release costs an L2 write-back, while a kernel boundary is cheap.
+//
+// Every floating-point step of the bin rule is one binary32 operation, rounded to nearest even,
+// in the documented order: contraction is off for this file, sqrtf and the division are the
+// correctly rounded forms.
+#include "ht_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace ht {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBlock = 256;
+constexpr int kGroupTiles = 64;  // largest group of tiles per peak workgroup (g.group_tiles)
+
+__device__ __forceinline__ EvDesc load_ev(const EvDesc& ev0, const EvDesc* evs)
+{
+  return evs ? evs[blockIdx.y] : ev0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Wave / block scans (wave64)
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+  const int lane = __lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Exclusive scan over the block (blockDim a multiple of 64, at most 1024). smem: >= 17 words.
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* smem, uint32_t* total)
+{
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) smem[w] = inc;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    uint32_t s = threadIdx.x < (unsigned)nw ? smem[threadIdx.x] : 0u;
+    uint32_t si = wave_incl_scan(s);
+    if (threadIdx.x < (unsigned)nw) smem[threadIdx.x] = si - s;
+    if (threadIdx.x == (unsigned)nw - 1) smem[16] = si;
+  }
+  __syncthreads();
+  uint32_t res = smem[w] + inc - v;
+  *total = smem[16];
+  __syncthreads();
+  return res;
+}
+
+__device__ uint32_t block_sum(uint32_t v, uint32_t* smem)
+{
+  uint32_t total;
+  block_excl_scan(v, smem, &total);
+  return total;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per-hit preparation (validity, per-hit values, half-sectors, cells)
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ int half_plane(float c, float s, float vx, float vy)
+{
+  float lhs = c * vy;
+  float rhs = s * vx;
+  float d = lhs - rhs;
+  return d >= 0.0f ? 1 : 0;
+}
+
+struct HitPrep {
+  int n;  // number of (theta, phi) cells, 0 when the hit votes nothing
+  int slab[4];
+  int s_theta, s_phi;
+  float x, r2, r, k;
+};
+
+__device__ HitPrep prep_hit(const DevGrid& g, float x, float y, float z)
+{
+  HitPrep h;
+  h.n = 0;
+  h.s_theta = h.s_phi = 0;
+  h.x = x;
+  h.r2 = h.r = h.k = 0.0f;
+  if (!(isfinite(x) && isfinite(y) && isfinite(z)) || y == 0.0f) return h;
+  float xx = x * x;
+  float yy = y * y;
+  float r2 = xx + yy;
+  if (!(r2 > 0.0f) || isinf(r2)) return h;
+  float r = sqrtf(r2);
+  float ty = y + y;
+  float k = 1.0f / ty;
+  int s_phi;
+  if (y > 0.0f) {
+    s_phi = 0;
+    for (int m = 1; m < g.n_phi; ++m) s_phi += half_plane(g.phi_cs[2 * m], g.phi_cs[2 * m + 1], x, y);
+  } else {
+    s_phi = g.n_phi;
+    for (int m = g.n_phi + 1; m < 2 * g.n_phi; ++m)
+      s_phi += half_plane(g.phi_cs[2 * m], g.phi_cs[2 * m + 1], x, y);
+  }
+  int s_th = 0;
+  for (int m = 1; m < 2 * g.n_theta; ++m) s_th += half_plane(g.th_cs[2 * m], g.th_cs[2 * m + 1], z, r);
+  const int p0 = s_phi >> 1;
+  const int p1 = (s_phi & 1) ? (p0 + 1 == g.n_phi ? 0 : p0 + 1) : (p0 == 0 ? g.n_phi - 1 : p0 - 1);
+  const int t0 = s_th >> 1;
+  const int t1 = (s_th & 1) ? t0 + 1 : t0 - 1;
+  h.slab[0] = t0 * g.n_phi + p0;
+  h.slab[1] = t0 * g.n_phi + p1;
+  h.n = 2;
+  if (t1 >= 0 && t1 < g.n_theta) {
+    h.slab[2] = t1 * g.n_phi + p0;
+    h.slab[3] = t1 * g.n_phi + p1;
+    h.n = 4;
+  }
+  h.s_theta = s_th;
+  h.s_phi = s_phi;
+  h.r2 = r2;
+  h.r = r;
+  h.k = k;
+  return h;
+}
+
+// Counts per slab: in LDS per workgroup, then one global atomic per (workgroup, slab) reserves
+// the workgroup's range of each slab list. slab_cnt starts at zero (the fill clears it again).
+__global__ __launch_bounds__(kBlock) void k_prep(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  __shared__ uint32_t lcnt[kMaxSlabs];
+  EvDesc e = load_ev(ev0, evs);
+  if ((int64_t)blockIdx.x * kBlock >= e.n_hits) return;  // uniform: whole block idle
+  for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) lcnt[i] = 0u;
+  __syncthreads();
+  const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  HitPrep p;
+  p.n = 0;
+  uint32_t local[4] = {0u, 0u, 0u, 0u};
+  if (h < e.n_hits) {
+    p = prep_hit(g, e.x[h], e.y[h], e.z[h]);
+    e.hit_rec[h] = make_float4(p.x, p.r2, p.k, 0.0f);
+    for (int q = 0; q < 4; ++q) {
+      int s = q < p.n ? p.slab[q] : -1;
+      e.hit_slab[4 * h + q] = s;
+      if (s >= 0) local[q] = atomicAdd(&lcnt[s], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) {
+    uint32_t c = lcnt[i];
+    if (c) lcnt[i] = atomicAdd(&e.slab_cnt[i], c);
+  }
+  __syncthreads();
+  if (h < e.n_hits)
+    for (int q = 0; q < p.n; ++q) e.hit_pos[4 * h + q] = lcnt[p.slab[q]] + local[q];
+}
+
+// Every workgroup scans the slab counts into LDS (they are few); workgroup 0 also publishes the
+// offsets for the fill. Then each hit's records go to their slab lists.
+__global__ __launch_bounds__(kBlock) void k_bucket(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  __shared__ uint32_t s_off[kMaxSlabs];
+  __shared__ uint32_t smem[32];
+  EvDesc e = load_ev(ev0, evs);
+  if (blockIdx.x > 0 && (int64_t)blockIdx.x * kBlock >= e.n_hits) return;
+  const int ns = g.n_slabs;
+  const int per = (ns + kBlock - 1) / kBlock;
+  const int beg = min(ns, (int)threadIdx.x * per);
+  const int end = min(ns, beg + per);
+  uint32_t sum = 0;
+  for (int i = beg; i < end; ++i) sum += e.slab_cnt[i];
+  uint32_t total;
+  uint32_t run = block_excl_scan(sum, smem, &total);
+  for (int i = beg; i < end; ++i) {
+    const uint32_t c = e.slab_cnt[i];
+    s_off[i] = run;
+    if (blockIdx.x == 0) e.slab_off[i] = run;
+    run += c;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) e.slab_off[ns] = total;
+  __syncthreads();
+  const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (h >= e.n_hits) return;
+  const float4 rec = e.hit_rec[h];
+  for (int q = 0; q < 4; ++q) {
+    const int s = e.hit_slab[4 * h + q];
+    if (s < 0) break;
+    e.list[s_off[s] + e.hit_pos[4 * h + q]] = rec;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Candidates (cells >= threshold) of one tile: unordered pushes into an LDS list, then a
+// bitonic sort, so that each tile's candidates are stored by ascending cell index.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void push_candidate(uint32_t* s_cand, uint32_t* s_n, uint32_t cap,
+                                               uint32_t off)
+{
+  uint32_t p = atomicAdd(s_n, 1u);
+  if (p < cap) s_cand[p] = off;
+}
+
+__device__ void lds_sort_u32(uint32_t* s, uint32_t n)
+{
+  if (n < 2) return;
+  uint32_t P = 2;
+  while (P < n) P <<= 1;
+  for (uint32_t i = n + threadIdx.x; i < P; i += blockDim.x) s[i] = 0xffffffffu;
+  __syncthreads();
+  for (uint32_t k = 2; k <= P; k <<= 1)
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        uint32_t l = i ^ j;
+        if (l > i) {
+          uint32_t a = s[i], b = s[l];
+          bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s[i] = b;
+            s[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// Called by the whole block after all pushes (and a barrier). `vals` holds the tile's counts
+// (the LDS tile in the fill, the matrix itself in the candidate scan).
+__device__ void finish_candidates(const DevGrid& g, const EvDesc& e, int tile, uint32_t tile_cell0,
+                                  uint32_t* s_cand, uint32_t n, const uint32_t* vals)
+{
+  if (n <= (uint32_t)g.cand_cap) {
+    lds_sort_u32(s_cand, n);
+    uint2* dst = e.cand + (size_t)tile * g.cand_cap;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint32_t off = s_cand[i];
+      dst[i] = make_uint2(tile_cell0 + off, vals[off]);
+    }
+  }
+  if (threadIdx.x == 0) e.tile_cnt[tile] = n;  // n > cand_cap marks an overflowed tile
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fill through an LDS tile of ROWS x n_b counters.
+// ---------------------------------------------------------------------------------------------
+template <int ROWS, bool VEC, bool EMIT, bool NT>
+__global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  extern __shared__ uint32_t smem[];
+  EvDesc e = load_ev(ev0, evs);
+  const int tile = blockIdx.x;
+  const int slab = tile / g.tiles_per_slab;
+  const int a0 = (tile - slab * g.tiles_per_slab) * ROWS;
+  const int rows = min(ROWS, g.n_a - a0);
+  const uint32_t nb = (uint32_t)g.n_b;
+  const uint32_t L = (uint32_t)rows * nb;
+  const uint32_t Lpad = ((uint32_t)ROWS * nb + 3u) & ~3u;
+  uint32_t* s_tile = smem;
+  uint32_t* s_cand = smem + Lpad;
+  uint32_t* s_ncand = s_cand + g.cand_cap;
+
+  u32x4* s4 = reinterpret_cast<u32x4*>(s_tile);
+  const u32x4 zero4 = {0u, 0u, 0u, 0u};
+  for (uint32_t i = threadIdx.x; i < Lpad / 4; i += kBlock) s4[i] = zero4;
+  if (EMIT && threadIdx.x == 0) *s_ncand = 0u;
+  // the slab counts of this event are consumed (k_bucket): leave them zero for the next use
+  if (tile == 0)
+    for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) e.slab_cnt[i] = 0u;
+  __syncthreads();
+
+  const uint32_t beg = e.slab_off[slab];
+  const uint32_t end = e.slab_off[slab + 1];
+  float a2r[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) a2r[r] = g.a2[min(a0 + r, g.n_a - 1)];
+  const float b_min = g.b_min, inv_db = g.inv_db, nb_f = g.nb_f;
+  for (uint32_t h = beg + threadIdx.x; h < end; h += kBlock) {
+    const float4 rec = e.list[h];
+    const float x = rec.x, r2 = rec.y, k = rec.z;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      if (r < rows) {
+        float ax = a2r[r] * x;
+        float num = r2 - ax;
+        float B = num * k;
+        float d = B - b_min;
+        float f = d * inv_db;
+        if (f >= 0.0f && f < nb_f) atomicAdd(&s_tile[(uint32_t)r * nb + (uint32_t)(int)f], 1u);
+      }
+    }
+  }
+  __syncthreads();
+
+  const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
+  uint32_t* dst = e.acc + cell0;
+  const uint32_t T = g.threshold;
+  if (VEC) {
+    u32x4* d4 = reinterpret_cast<u32x4*>(dst);
+    for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) {
+      u32x4 v = s4[i];
+      if (NT) __builtin_nontemporal_store(v, d4 + i);
+      else d4[i] = v;
+      if (EMIT) {
+        uint32_t m = max(max(v.x, v.y), max(v.z, v.w));
+        if (m >= T) {
+          if (v.x >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i);
+          if (v.y >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 1);
+          if (v.z >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 2);
+          if (v.w >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 3);
+        }
+      }
+    }
+  } else {
+    for (uint32_t i = threadIdx.x; i < L; i += kBlock) {
+      uint32_t v = s_tile[i];
+      if (NT) __builtin_nontemporal_store(v, dst + i);
+      else dst[i] = v;
+      if (EMIT && v >= T) push_candidate(s_cand, s_ncand, g.cand_cap, i);
+    }
+  }
+  if (EMIT) {
+    __syncthreads();
+    finish_candidates(g, e, tile, cell0, s_cand, *s_ncand, s_tile);
+  }
+}
+
+// Candidates of an arbitrary matrix: one coalesced read of each tile.
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_cand_scan(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  extern __shared__ uint32_t smem[];
+  EvDesc e = load_ev(ev0, evs);
+  const int tile = blockIdx.x;
+  const int slab = tile / g.tiles_per_slab;
+  const int a0 = (tile - slab * g.tiles_per_slab) * g.rows;
+  const int rows = min(g.rows, g.n_a - a0);
+  const uint32_t nb = (uint32_t)g.n_b;
+  const uint32_t L = (uint32_t)rows * nb;
+  uint32_t* s_cand = smem;
+  uint32_t* s_ncand = s_cand + g.cand_cap;
+  if (threadIdx.x == 0) *s_ncand = 0u;
+  __syncthreads();
+  const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
+  const uint32_t* src = e.acc + cell0;
+  const uint32_t T = g.threshold;
+  if (VEC) {
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+    for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) {
+      u32x4 v = __builtin_nontemporal_load(s4 + i);
+      uint32_t m = max(max(v.x, v.y), max(v.z, v.w));
+      if (m >= T) {
+        if (v.x >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i);
+        if (v.y >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 1);
+        if (v.z >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 2);
+        if (v.w >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 3);
+      }
+    }
+  } else {
+    for (uint32_t i = threadIdx.x; i < L; i += kBlock) {
+      uint32_t v = src[i];
+      if (v >= T) push_candidate(s_cand, s_ncand, g.cand_cap, i);
+    }
+  }
+  __syncthreads();
+  finish_candidates(g, e, tile, cell0, s_cand, *s_ncand, src);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Peak test: strict maximum under (votes, -index) over the 3^4 box, phi periodic.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void cell_coords(const DevGrid& g, uint32_t c, uint32_t* t, uint32_t* p,
+                                            uint32_t* a, uint32_t* b)
+{
+  const uint32_t nb = (uint32_t)g.n_b, na = (uint32_t)g.n_a, np = (uint32_t)g.n_phi;
+  *b = c % nb;
+  uint32_t q = c / nb;
+  *a = q % na;
+  q /= na;
+  *p = q % np;
+  *t = q / np;
+}
+
+struct __attribute__((packed, aligned(4))) U32x3 {
+  uint32_t v0, v1, v2;
+};
+
+// Every neighbour row is fetched before any comparison (no early exit), so a candidate costs one
+// memory round trip: 27 rows of three cells, one 12-byte load each. The window of a row starts
+// at min(max(b, 1) - 1, n_b - 3), so it stays inside the row; absent rows (outside theta or A)
+// read the candidate's own row and are masked out.
+__device__ bool is_peak(const DevGrid& g, const uint32_t* __restrict__ acc, uint32_t c, uint32_t v)
+{
+  const uint32_t nb = (uint32_t)g.n_b, na = (uint32_t)g.n_a, np = (uint32_t)g.n_phi;
+  uint32_t t, p, a, b;
+  cell_coords(g, c, &t, &p, &a, &b);
+  const uint32_t pm = p == 0 ? np - 1 : p - 1;
+  const uint32_t pp1 = p + 1 == np ? 0 : p + 1;
+  if (nb < 3) {
+    // narrow rows: one load per neighbour
+    bool beaten = false;
+    for (int k = 0; k < 27; ++k) {
+      const int dt = k / 9 - 1, dp = (k / 3) % 3 - 1, da = k % 3 - 1;
+      const int tt = (int)t + dt, aa = (int)a + da;
+      if (tt < 0 || tt >= g.n_theta || aa < 0 || aa >= (int)na) continue;
+      const uint32_t pp = dp < 0 ? pm : (dp > 0 ? pp1 : p);
+      const uint32_t rowc = (((uint32_t)tt * np + pp) * na + (uint32_t)aa) * nb;
+      for (int db = -1; db <= 1; ++db) {
+        const int bb = (int)b + db;
+        if (bb < 0 || bb >= (int)nb || (dt == 0 && dp == 0 && da == 0 && db == 0)) continue;
+        const uint32_t n = rowc + (uint32_t)bb;
+        const uint32_t w = acc[n];
+        beaten |= w > v || (w == v && n < c);
+      }
+    }
+    return !beaten;
+  }
+  const uint32_t w0 = min(max(b, 1u) - 1u, nb - 3u);
+  U32x3 row[27];
+  uint32_t base[27];
+  bool rv[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) {
+    const int dt = k / 9 - 1, dp = (k / 3) % 3 - 1, da = k % 3 - 1;
+    const int tt = (int)t + dt, aa = (int)a + da;
+    rv[k] = tt >= 0 && tt < g.n_theta && aa >= 0 && aa < (int)na;
+    const uint32_t pp = dp < 0 ? pm : (dp > 0 ? pp1 : p);
+    base[k] = (rv[k] ? (((uint32_t)tt * np + pp) * na + (uint32_t)aa) * nb : c - b) + w0;
+    row[k] = *reinterpret_cast<const U32x3*>(acc + base[k]);
+  }
+  bool beaten = false;
+#pragma unroll
+  for (int k = 0; k < 27; ++k) {
+    const bool centre_row = k == 13;
+    const uint32_t vals[3] = {row[k].v0, row[k].v1, row[k].v2};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const uint32_t bb = w0 + (uint32_t)q;
+      // inside the window; neighbour iff |bb - b| <= 1 and not the candidate itself
+      const bool near = bb + 1u >= b && bb <= b + 1u && !(centre_row && bb == b);
+      const uint32_t n = base[k] + (uint32_t)q;
+      beaten |= rv[k] && near && (vals[q] > v || (vals[q] == v && n < c));
+    }
+  }
+  return !beaten;
+}
+
+__device__ __forceinline__ void tile_range(const DevGrid& g, int tile, uint32_t* cell0, uint32_t* L)
+{
+  const int slab = tile / g.tiles_per_slab;
+  const int a0 = (tile - slab * g.tiles_per_slab) * g.rows;
+  const int rows = min(g.rows, g.n_a - a0);
+  *cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * (uint32_t)g.n_b;
+  *L = (uint32_t)rows * (uint32_t)g.n_b;
+}
+
+// Wave 0 of the block: s_pre = exclusive prefix over the group's tiles of counts[] (tiles whose
+// candidates overflowed count 0 when counts is tile_cnt); s_ovf marks the overflowed tiles.
+__device__ void group_prefix(const DevGrid& g, const EvDesc& e, int t0, int nt, uint32_t* s_pre,
+                             uint32_t* s_ovf, const uint32_t* counts)
+{
+  // tiles nt..kGroupTiles-1 count zero, so s_pre[nt..kGroupTiles] all equal the group total
+  if (threadIdx.x < kGroupTiles) {
+    const int i = threadIdx.x;
+    uint32_t c = i < nt ? counts[t0 + i] : 0u;
+    const uint32_t ovf = i < nt && e.tile_cnt[t0 + i] > (uint32_t)g.cand_cap ? 1u : 0u;
+    s_ovf[i] = ovf;
+    if (ovf && counts == e.tile_cnt) c = 0u;
+    const uint32_t inc = wave_incl_scan(c);
+    s_pre[i + 1] = inc;
+    if (i == 0) s_pre[0] = 0u;
+  }
+}
+
+// Largest t with pre[t] <= f, given pre[0] <= f < pre[kGroupTiles].
+__device__ __forceinline__ int group_tile_of(const uint32_t* pre, uint32_t f)
+{
+  int lo = 0, hi = kGroupTiles;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= f) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One workgroup per group of tiles: every stored candidate of the group is tested at once
+// (thread per candidate), the peaks are compacted in order to the front of the group's
+// candidate slots, and the per-tile and per-group peak counts are written. Tiles whose
+// candidates overflowed their slots are counted by a dense pass, one wave per tile.
+__global__ __launch_bounds__(kBlock) void k_peak_mark(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  __shared__ uint32_t s_pre[kGroupTiles + 1];
+  __shared__ uint32_t s_ovf[kGroupTiles];
+  __shared__ uint32_t s_pk[kGroupTiles];
+  __shared__ uint32_t smem[32];
+  EvDesc e = load_ev(ev0, evs);
+  const int t0 = blockIdx.x * g.group_tiles;
+  const int nt = min(g.group_tiles, g.n_tiles - t0);
+  if (threadIdx.x < kGroupTiles) s_pk[threadIdx.x] = 0u;
+  group_prefix(g, e, t0, nt, s_pre, s_ovf, e.tile_cnt);
+  __syncthreads();
+  const uint32_t total = s_pre[kGroupTiles];
+  const size_t cap = (size_t)g.cand_cap;
+  uint2* region = e.cand + (size_t)t0 * cap;
+  const uint32_t* acc = e.acc;
+  uint32_t run = 0;
+  for (uint32_t base = 0; base < total; base += kBlock) {
+    const uint32_t f = base + threadIdx.x;
+    bool pk = false;
+    uint2 cv = make_uint2(0u, 0u);
+    int tl = 0;
+    if (f < total) {
+      tl = group_tile_of(s_pre, f);
+      cv = region[(size_t)tl * cap + (f - s_pre[tl])];
+      pk = is_peak(g, acc, cv.x, cv.y);
+    }
+    uint32_t tot;
+    const uint32_t pos = run + block_excl_scan(pk ? 1u : 0u, smem, &tot);
+    // every candidate of this chunk has been read (barriers in the scan); pos <= f, and each
+    // unread candidate sits at a slot index >= its flat index > pos, so the compaction is safe
+    if (pk) {
+      region[pos] = cv;
+      atomicAdd(&s_pk[tl], 1u);
+    }
+    run += tot;
+    __syncthreads();
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int tl = wave; tl < nt; tl += kBlock / 64) {
+    if (!s_ovf[tl]) continue;
+    uint32_t cell0, L;
+    tile_range(g, t0 + tl, &cell0, &L);
+    uint32_t mine = 0;
+    for (uint32_t i = lane; i < L; i += 64) {
+      const uint32_t c = cell0 + i;
+      const uint32_t v = acc[c];
+      if (v >= g.threshold && is_peak(g, acc, c, v)) ++mine;
+    }
+    mine = wave_sum(mine);
+    if (lane == 0) s_pk[tl] = mine;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nt) e.tile_pk[t0 + threadIdx.x] = s_pk[threadIdx.x];
+  const uint32_t gsum = block_sum(threadIdx.x < kGroupTiles ? s_pk[threadIdx.x] : 0u, smem);
+  if (threadIdx.x == 0) e.group_pk[blockIdx.x] = gsum;
+}
+
+// One workgroup per group: its output offset is the sum of the earlier groups' totals; the
+// group's staged peaks are copied out in order, overflowed tiles are re-scanned densely.
+__global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  __shared__ uint32_t s_out[kGroupTiles + 1];
+  __shared__ uint32_t s_stg[kGroupTiles + 1];
+  __shared__ uint32_t s_ovf[kGroupTiles];
+  __shared__ uint32_t smem[32];
+  EvDesc e = load_ev(ev0, evs);
+  const int G = blockIdx.x;
+  const int t0 = G * g.group_tiles;
+  const int nt = min(g.group_tiles, g.n_tiles - t0);
+  uint32_t part = 0;
+  for (int i = threadIdx.x; i < G; i += kBlock) part += e.group_pk[i];
+  const uint32_t base32 = block_sum(part, smem);
+  const int64_t base = (int64_t)base32;
+  if (G == (int)gridDim.x - 1 && threadIdx.x == 0) *e.n_found = base + e.group_pk[G];
+  if (base >= e.cap) return;  // uniform
+  group_prefix(g, e, t0, nt, s_out, s_ovf, e.tile_pk);
+  __syncthreads();
+  // staged prefix: peaks of the tiles that were not overflowed
+  if (threadIdx.x < kGroupTiles) {
+    const int i = threadIdx.x;
+    const uint32_t c = (i < nt && !s_ovf[i]) ? e.tile_pk[t0 + i] : 0u;
+    const uint32_t inc = wave_incl_scan(c);
+    s_stg[i + 1] = inc;
+    if (i == 0) s_stg[0] = 0u;
+  }
+  __syncthreads();
+  const uint32_t staged = s_stg[kGroupTiles];
+  const uint2* region = e.cand + (size_t)t0 * (size_t)g.cand_cap;
+  for (uint32_t j = threadIdx.x; j < staged; j += kBlock) {
+    const int tl = group_tile_of(s_stg, j);
+    const int64_t o = base + s_out[tl] + (j - s_stg[tl]);
+    if (o < e.cap) {
+      const uint2 cv = region[j];
+      ht_peak pk;
+      pk.cell = cv.x;
+      pk.votes = cv.y;
+      e.out[o] = pk;
+    }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t* acc = e.acc;
+  for (int tl = wave; tl < nt; tl += kBlock / 64) {
+    if (!s_ovf[tl]) continue;
+    uint32_t cell0, L;
+    tile_range(g, t0 + tl, &cell0, &L);
+    uint32_t run = 0;
+    for (uint32_t b0 = 0; b0 < L; b0 += 64) {
+      const uint32_t i = b0 + lane;
+      bool pk = false;
+      uint32_t c = 0, v = 0;
+      if (i < L) {
+        c = cell0 + i;
+        v = acc[c];
+        pk = v >= g.threshold && is_peak(g, acc, c, v);
+      }
+      const uint64_t m = __ballot(pk);
+      const int64_t o = base + s_out[tl] + run + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (pk && o < e.cap) {
+        ht_peak q;
+        q.cell = c;
+        q.votes = v;
+        e.out[o] = q;
+      }
+      run += (uint32_t)__popcll(m);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Plain fill: zero the matrix, then one global atomicAdd per vote. One block per hit, its
+// threads over the A bins (the decomposition the paper describes, kept as a baseline).
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_zero_acc(DevGrid g, EvDesc ev0, const EvDesc* evs,
+                                                     uint64_t cells)
+{
+  EvDesc e = load_ev(ev0, evs);
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < cells; i += stride)
+    e.acc[i] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_atomic(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  EvDesc e = load_ev(ev0, evs);
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) e.slab_cnt[i] = 0u;
+  const int64_t h = blockIdx.x;
+  if (h >= e.n_hits) return;
+  int slabs[4];
+  int ns = 0;
+  for (int q = 0; q < 4; ++q) {
+    int s = e.hit_slab[4 * h + q];
+    if (s >= 0) slabs[ns++] = s;
+  }
+  if (ns == 0) return;
+  const float4 rec = e.hit_rec[h];
+  const float x = rec.x, r2 = rec.y, k = rec.z;
+  for (int i = threadIdx.x; i < g.n_a; i += kBlock) {
+    float ax = g.a2[i] * x;
+    float num = r2 - ax;
+    float B = num * k;
+    float d = B - g.b_min;
+    float f = d * g.inv_db;
+    if (f >= 0.0f && f < g.nb_f) {
+      const uint32_t j = (uint32_t)(int)f;
+      for (int q = 0; q < ns; ++q)
+        atomicAdd(&e.acc[((uint64_t)slabs[q] * g.n_a + i) * g.n_b + j], 1u);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_debug_hits(DevGrid g, const float* x, const float* y,
+                                                       const float* z, int64_t n, int32_t* info,
+                                                       float* vals, int32_t* slabs)
+{
+  const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (h >= n) return;
+  HitPrep p = prep_hit(g, x[h], y[h], z[h]);
+  info[4 * h + 0] = p.n > 0;
+  info[4 * h + 1] = p.s_theta;
+  info[4 * h + 2] = p.s_phi;
+  info[4 * h + 3] = p.n;
+  vals[3 * h + 0] = p.r2;
+  vals[3 * h + 1] = p.r;
+  vals[3 * h + 2] = p.k;
+  for (int q = 0; q < 4; ++q) slabs[4 * h + q] = q < p.n ? p.slab[q] : -1;
+}
+
+template <int ROWS, bool NT>
+hipError_t launch_fill_rows(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                            bool vec, bool emit, size_t lds, hipStream_t s)
+{
+  dim3 grid(g.n_tiles, n_ev);
+  if (vec) {
+    if (emit) hipLaunchKernelGGL((k_fill<ROWS, true, true, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
+    else hipLaunchKernelGGL((k_fill<ROWS, true, false, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
+  } else {
+    if (emit) hipLaunchKernelGGL((k_fill<ROWS, false, true, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
+    else hipLaunchKernelGGL((k_fill<ROWS, false, false, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
+  }
+  return hipGetLastError();
+}
+
+template <bool NT>
+hipError_t launch_fill_nt(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev, bool vec,
+                          bool emit, size_t lds, hipStream_t s)
+{
+  switch (g.rows) {
+    case 1: return launch_fill_rows<1, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
+    case 2: return launch_fill_rows<2, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
+    case 4: return launch_fill_rows<4, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
+    case 8: return launch_fill_rows<8, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
+    case 16: return launch_fill_rows<16, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
+    case 32: return launch_fill_rows<32, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
+    case 64: return launch_fill_rows<64, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int n_groups(const DevGrid& g) { return (g.n_tiles + g.group_tiles - 1) / g.group_tiles; }
+
+size_t fill_lds_bytes(const DevGrid& g)
+{
+  const size_t lpad = (((size_t)g.rows * g.n_b) + 3) & ~(size_t)3;
+  return (lpad + (size_t)g.cand_cap + 4) * sizeof(uint32_t);
+}
+
+hipError_t launch_prep(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                       int64_t max_hits, hipStream_t s)
+{
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, (max_hits + kBlock - 1) / kBlock);
+  if (max_hits > 0) hipLaunchKernelGGL(k_prep, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
+  hipLaunchKernelGGL(k_bucket, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                       bool emit, hipStream_t s)
+{
+  const bool vec = (g.n_b % 4) == 0;
+  const size_t lds = fill_lds_bytes(g);
+  if (g.nt_store) return launch_fill_nt<true>(g, ev0, evs, n_ev, vec, emit, lds, s);
+  return launch_fill_nt<false>(g, ev0, evs, n_ev, vec, emit, lds, s);
+}
+
+hipError_t launch_candidates(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                             hipStream_t s)
+{
+  const size_t lds = ((size_t)g.cand_cap + 4) * sizeof(uint32_t);
+  dim3 grid(g.n_tiles, n_ev);
+  if (g.n_b % 4 == 0) hipLaunchKernelGGL(k_cand_scan<true>, grid, dim3(kBlock), lds, s, g, ev0, evs);
+  else hipLaunchKernelGGL(k_cand_scan<false>, grid, dim3(kBlock), lds, s, g, ev0, evs);
+  return hipGetLastError();
+}
+
+hipError_t launch_peaks(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                        hipStream_t s)
+{
+  dim3 grid(n_groups(g), n_ev);
+  hipLaunchKernelGGL(k_peak_mark, grid, dim3(kBlock), 0, s, g, ev0, evs);
+  hipLaunchKernelGGL(k_peak_write, grid, dim3(kBlock), 0, s, g, ev0, evs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_atomic(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                              int64_t max_hits, hipStream_t s)
+{
+  const uint64_t cells = (uint64_t)g.n_slabs * g.n_a * g.n_b;
+  hipLaunchKernelGGL(k_zero_acc, dim3(4096, n_ev), dim3(kBlock), 0, s, g, ev0, evs, cells);
+  hipLaunchKernelGGL(k_fill_atomic, dim3((unsigned)std::max<int64_t>(max_hits, 1), n_ev), dim3(kBlock), 0,
+                     s, g, ev0, evs);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_hits(const DevGrid& g, const float* x, const float* y, const float* z,
+                             int64_t n, int32_t* info, float* vals, int32_t* slabs, hipStream_t s)
+{
+  if (n > 0)
+    hipLaunchKernelGGL(k_debug_hits, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       g, x, y, z, n, info, vals, slabs);
+  return hipGetLastError();
+}
+
+}  // namespace ht

@@ -1,0 +1,121 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every declared symbol,
+computes the bin-rule tables bit-identically to the oracle, and rejects bad arguments on the host
+before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1507_03074_amd import binding as B
+from paper_1507_03074_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return B.lib()
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(ht_\w+)\s*\(", text, re.M))
+    return names
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert {"ht_fill", "ht_peaks", "ht_fill_peaks_batch", "ht_serve_submit", "ht_serve_poll"} <= names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(B.EXPORTS) == names
+
+
+GRIDS = [synth.WORKLOADS[0].grid, synth.WORKLOADS[1].grid, synth.WORKLOADS[4].grid,
+         synth.GridSpec(3, 5, 7, 9, a_min=-1500.0, a_max=1300.0, b_min=-1100.0, b_max=1700.0,
+                        threshold=2),
+         synth.GridSpec(2, 7, 100, 37, a_min=-999.0, a_max=1234.5, b_min=-3.0, b_max=7.25)]
+
+
+@pytest.mark.parametrize("spec", GRIDS)
+def test_tables_bit_identical_to_oracle(lib, spec):
+    from oracle import oracle
+    a2, inv, phi, th = B.ht_tables(spec)
+    oa2, oinv, ophi, oth = oracle.tables(oracle.OracleGrid(*spec.as_tuple()))
+    assert a2.tobytes() == oa2.tobytes()
+    assert np.float32(inv).tobytes() == np.float32(oinv).tobytes()
+    assert phi.tobytes() == ophi.tobytes()
+    assert th.tobytes() == oth.tobytes()
+
+
+def test_invalid_grid_rejected_on_host(lib):
+    bad = synth.GridSpec(4, 2, 64, 64)
+    g = B.make_grid(bad)
+    dummy = ctypes.c_void_p(256)   # never dereferenced: validation fails first
+    rc = lib.ht_fill(ctypes.byref(g), None, None, None, 0, dummy, None)
+    assert rc == B.HT_EINVAL and "n_phi" in B.last_error()
+    rc = lib.ht_peaks(ctypes.byref(g), dummy, None, 0, dummy, None)
+    assert rc == B.HT_EINVAL and "n_phi" in B.last_error()
+    for spec in [synth.GridSpec(64, 64, 4096, 4096), synth.GridSpec(4, 16, 64, 64, threshold=0),
+                 synth.GridSpec(4, 16, 64, 64, a_min=5.0, a_max=5.0),
+                 synth.GridSpec(200, 100, 8, 8)]:
+        g = B.make_grid(spec)
+        assert lib.ht_fill(ctypes.byref(g), None, None, None, 0, dummy, None) == B.HT_EINVAL
+        assert "grid" in B.last_error() or "cells" in B.last_error() or "threshold" in B.last_error() \
+            or "n_theta" in B.last_error()
+
+
+def test_bad_arguments_rejected_on_host(lib):
+    g = B.make_grid(synth.WORKLOADS[0].grid)
+    # negative hit count, missing matrix, missing hit arrays
+    assert lib.ht_fill(ctypes.byref(g), None, None, None, -1, ctypes.c_void_p(16), None) == B.HT_EINVAL
+    assert lib.ht_fill(ctypes.byref(g), None, None, None, 0, None, None) == B.HT_EINVAL
+    assert lib.ht_fill(ctypes.byref(g), None, None, None, 5, ctypes.c_void_p(16), None) == B.HT_EINVAL
+    # peaks: capacity > 0 without an output array, or no n_found
+    assert lib.ht_peaks(ctypes.byref(g), ctypes.c_void_p(16), None, 4, ctypes.c_void_p(16), None) == B.HT_EINVAL
+    assert lib.ht_peaks(ctypes.byref(g), ctypes.c_void_p(16), None, 0, None, None) == B.HT_EINVAL
+    ev = (B.Event * 1)(B.Event(0, -3, 0, 0))
+    assert lib.ht_fill_peaks_batch(ctypes.byref(g), ev, 1, None, None, None, ctypes.c_void_p(16),
+                                   None, ctypes.c_void_p(16), None) == B.HT_EINVAL
+    assert lib.ht_fill_peaks_batch(ctypes.byref(g), ev, -1, None, None, None, None, None, None,
+                                   None) == B.HT_EINVAL
+
+
+def test_serve_options_validated_on_host(lib):
+    g = B.make_grid(synth.WORKLOADS[0].grid)
+    srv = ctypes.c_void_p()
+    for opts in [B.ServeOpts(0, 16, 100, 4, 2, 8, 0), B.ServeOpts(1 << 30, 0, 100, 4, 2, 8, 0),
+                 B.ServeOpts(1 << 30, 16, 100, 0, 2, 8, 0), B.ServeOpts(1 << 30, 16, 100, 4, 0, 8, 0),
+                 B.ServeOpts(1 << 30, 16, 100, 4, 2, 0, 0)]:
+        assert lib.ht_serve_create(ctypes.byref(g), ctypes.byref(opts), ctypes.byref(srv)) == B.HT_EINVAL
+        assert not srv.value
+    assert lib.ht_serve_destroy(None) == B.HT_OK
+    t = ctypes.c_uint64()
+    assert lib.ht_serve_submit(None, None, None, None, 0, ctypes.byref(t)) == B.HT_EINVAL
+
+
+def test_tiling_covers_the_matrix(lib):
+    for spec in GRIDS:
+        t = B.ht_tiling(spec)
+        rows = t["rows"]
+        assert rows >= 1 and rows & (rows - 1) == 0 and rows <= 64
+        tiles_per_slab = -(-spec.n_a // rows)
+        assert t["n_tiles"] == spec.n_theta * spec.n_phi * tiles_per_slab
+        assert t["cand_cap"] & (t["cand_cap"] - 1) == 0
+        if t["lds_fill"]:
+            assert rows * spec.n_b * 4 <= 65536
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libht.so")
+    with pytest.raises(B.HTError):
+        B.lib()

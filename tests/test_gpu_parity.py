@@ -1,0 +1,393 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+Vote counts are integers and the bin rule is fixed binary32 arithmetic on both sides, so every
+comparison here is exact: vote matrices element by element, peak lists entry by entry.
+"""
+import ctypes
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1507_03074_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CFG0 = synth.WORKLOADS[0].grid
+CFG1 = synth.WORKLOADS[1].grid
+CFG4 = synth.WORKLOADS[4].grid
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    from paper_1507_03074_amd import binding as B
+    if not os.path.exists(B.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    B.lib()
+    return B
+
+
+@pytest.fixture()
+def env_tiling():
+    keys = ("HT_FILL_ROWS", "HT_CAND_CAP", "HT_FILL_LDS_BYTES")
+    saved = {k: os.environ.get(k) for k in keys}
+    yield
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
+def oracle_run(spec, x, y, z):
+    from oracle import oracle
+    g = oracle.OracleGrid(*spec.as_tuple())
+    M, votes = oracle.fill(g, x, y, z)
+    cells, vv, n = oracle.peaks(g, M)
+    return M, votes, cells, vv, n
+
+
+def gpu_fused(B, spec, x, y, z, capacity=1 << 16):
+    import torch
+    xd, yd, zd = B.hits_to_device(x, y, z)
+    acc, cells, votes, n = B.fill_peaks(spec, xd, yd, zd, capacity=capacity)
+    torch.cuda.synchronize()
+    return B.as_u32(acc), cells, votes, n
+
+
+def assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, tag=""):
+    assert gM.shape == M.shape
+    if not np.array_equal(gM, M):
+        bad = np.argwhere(gM != M)
+        raise AssertionError("%s: %d cells differ, first %s gpu=%d oracle=%d" % (
+            tag, len(bad), bad[0], gM[tuple(bad[0])], M[tuple(bad[0])]))
+    assert gn == on, (tag, gn, on)
+    assert np.array_equal(gc, oc) and np.array_equal(gv, ov), tag
+
+
+def random_hits(seed, n, spread=1000.0):
+    rng = np.random.default_rng(seed)
+    return synth.uniform_hits(rng, n, spread, 2.5 * spread)
+
+
+# ---------------------------------------------------------------------------------------------
+def test_hit_values_match_oracle(gpu):
+    """r2, sqrt(r2), 1/(2y), half-sectors and cells of the device prep equal the oracle's bits."""
+    import torch
+    from oracle import oracle
+    B = gpu
+    rng = np.random.default_rng(1)
+    n = 1 << 20
+    mag = 10.0 ** rng.uniform(-3, 4, (3, n))
+    sign = np.where(rng.random((3, n)) < 0.5, -1.0, 1.0)
+    x, y, z = (mag * sign).astype(np.float32)
+    # exact half-sector boundaries and degenerate values
+    ang = np.arange(64) * np.pi / 16
+    x[:64] = (500 * np.cos(ang)).astype(np.float32)
+    y[:64] = (500 * np.sin(ang)).astype(np.float32)
+    x[64:80] = [0, 0, 1, np.inf, np.nan, 1e30, -1e30, 3e19, 1e-30, 5, -5, 0, 7, 1e-20, 2e-23, 1e38]
+    y[64:80] = [0, 1, 0, 1, 1, 1e30, 1e-30, 3e19, 1e-30, -0.0, 0.0, -3, np.inf, 1e-20, 2e-23, 1e38]
+    for spec in (CFG0, CFG4, synth.GridSpec(3, 5, 7, 9, threshold=2)):
+        say("hit values: grid", spec.shape)
+        xd, yd, zd = B.hits_to_device(x, y, z)
+        info, vals, slabs = B.ht_debug_hit_values(spec, xd, yd, zd)
+        torch.cuda.synchronize()
+        info, vals, slabs = info.cpu().numpy(), vals.cpu().numpy(), slabs.cpu().numpy()
+        o = oracle.hit_info(oracle.OracleGrid(*spec.as_tuple()), x, y, z)
+        assert np.array_equal(info[:, 0].astype(bool), o["valid"])
+        v = o["valid"]
+        assert np.array_equal(info[v, 1], o["s_theta"][v])
+        assert np.array_equal(info[v, 2], o["s_phi"][v])
+        assert np.array_equal(info[:, 3], o["n_cells"])
+        for col, key in ((0, "r2"), (1, "r"), (2, "k")):
+            assert vals[v, col].tobytes() == o[key][v].tobytes(), key
+        oslab = np.where(o["cells"][:, :, 0] >= 0, o["cells"][:, :, 0] * spec.n_phi + o["cells"][:, :, 1], -1)
+        assert np.array_equal(slabs, oslab)
+
+
+def test_cfg0_events_bit_exact(gpu):
+    B = gpu
+    nonempty = 0
+    for e in range(100):
+        ev = synth.make_event(0, e)
+        if e % 25 == 0:
+            say("workload 0 event", e)
+        gM, gc, gv, gn = gpu_fused(B, CFG0, ev.x, ev.y, ev.z)
+        M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
+        assert_same(CFG0, gM, gc, gv, gn, M, oc, ov, on, "event %d" % e)
+        assert int(gM.sum(dtype=np.int64)) == votes
+        nonempty += on > 0
+    assert nonempty >= 40
+
+
+def test_fill_paths_agree(gpu):
+    """ht_fill (LDS tiles), ht_fill_atomic (global atomics) and the fused call give one matrix;
+    ht_peaks on it gives the oracle's peaks."""
+    import torch
+    B = gpu
+    for e in range(5):
+        ev = synth.make_event(0, 200 + e)
+        say("fill paths: workload 0 event", 200 + e)
+        xd, yd, zd = B.hits_to_device(ev.x, ev.y, ev.z)
+        a1 = B.fill(CFG0, xd, yd, zd)
+        a2 = B.fill(CFG0, xd, yd, zd, atomic=True)
+        a3, _, _, _ = B.fill_peaks(CFG0, xd, yd, zd)
+        torch.cuda.synchronize()
+        M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
+        for a in (a1, a2, a3):
+            assert np.array_equal(B.as_u32(a), M)
+        c, v, n = B.peaks(CFG0, a1)
+        assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
+
+
+@pytest.mark.parametrize("shape,T", [((2, 4, 8, 8), 3), ((3, 5, 7, 9), 3), ((4, 16, 64, 64), 4),
+                                     ((1, 3, 5, 1), 2), ((2, 3, 40, 130), 5), ((3, 4, 33, 64), 6)])
+def test_peaks_on_arbitrary_matrices(gpu, shape, T):
+    import torch
+    from oracle import oracle
+    B = gpu
+    say("peaks on a random matrix", shape)
+    rng = np.random.default_rng(sum(shape) + T)
+    M = rng.integers(0, 4, size=shape).astype(np.uint32)
+    spikes = rng.random(shape) < 0.03
+    M[spikes] += rng.integers(3, 12, size=int(spikes.sum())).astype(np.uint32)
+    spec = synth.GridSpec(*shape, threshold=T)
+    acc = torch.from_numpy(M.view(np.int32).copy()).cuda()
+    c, v, n = B.peaks(spec, acc)
+    oc, ov, on = oracle.peaks(oracle.OracleGrid(*spec.as_tuple()), M)
+    assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
+
+
+RAGGED = [
+    synth.GridSpec(3, 5, 7, 9, a_min=-1500.0, a_max=1300.0, b_min=-1100.0, b_max=1700.0, threshold=2),
+    synth.GridSpec(2, 7, 100, 37, a_min=-999.0, a_max=1234.5, b_min=-1500.0, b_max=2000.0, threshold=3),
+    synth.GridSpec(4, 16, 130, 66, threshold=4),
+    synth.GridSpec(1, 3, 1, 1, threshold=1),
+    synth.GridSpec(5, 3, 257, 1000, threshold=3),
+    synth.GridSpec(2, 4, 3, 20000, threshold=2),   # rows too wide for an LDS tile: atomic fill
+]
+
+
+@pytest.mark.parametrize("spec", RAGGED, ids=lambda s: "x".join(map(str, s.shape)))
+def test_ragged_grids_bit_exact(gpu, spec):
+    B = gpu
+    for seed in range(3):
+        say("ragged grid", spec.shape, "seed", seed)
+        x, y, z = random_hits(seed, 300 if spec.n_b < 10000 else 60)
+        gM, gc, gv, gn = gpu_fused(B, spec, x, y, z)
+        M, votes, oc, ov, on = oracle_run(spec, x, y, z)
+        assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "seed %d" % seed)
+
+
+@pytest.mark.parametrize("rows", [1, 2, 4, 8, 16, 32, 64])
+def test_every_tile_shape_bit_exact(gpu, env_tiling, rows):
+    B = gpu
+    os.environ["HT_FILL_ROWS"] = str(rows)
+    for spec, ev in ((CFG0, synth.make_event(0, 3)), (synth.GridSpec(4, 16, 100, 40, threshold=4),
+                                                       synth.make_event(0, 4))):
+        say("tile rows", rows, "grid", spec.shape)
+        gM, gc, gv, gn = gpu_fused(B, spec, ev.x, ev.y, ev.z)
+        M, votes, oc, ov, on = oracle_run(spec, ev.x, ev.y, ev.z)
+        assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "rows %d" % rows)
+
+
+def test_candidate_overflow_uses_dense_path(gpu, env_tiling):
+    """With 2 candidate slots per tile, crowded tiles overflow and are searched densely; the
+    results must not change."""
+    B = gpu
+    os.environ["HT_CAND_CAP"] = "2"
+    for e in (0, 1, 2):
+        say("candidate overflow, workload 0 event", e)
+        ev = synth.make_event(0, e)
+        gM, gc, gv, gn = gpu_fused(B, CFG0, ev.x, ev.y, ev.z)
+        M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
+        assert_same(CFG0, gM, gc, gv, gn, M, oc, ov, on)
+        import torch
+        acc = torch.from_numpy(M.view(np.int32).copy()).cuda()
+        c, v, n = B.peaks(CFG0, acc)
+        assert n == on and np.array_equal(c, oc)
+
+
+def test_paper_sized_events_bit_exact(gpu):
+    """The 4x16x1024x1024 workload (5000 hits) in the configuration the benchmark times."""
+    B = gpu
+    for e in (0, 1, 2):
+        say("workload 1 event", e)
+        ev = synth.make_event(1, e)
+        gM, gc, gv, gn = gpu_fused(B, CFG1, ev.x, ev.y, ev.z)
+        M, votes, oc, ov, on = oracle_run(CFG1, ev.x, ev.y, ev.z)
+        assert_same(CFG1, gM, gc, gv, gn, M, oc, ov, on, "event %d" % e)
+        assert on > 100
+
+
+def test_empty_and_degenerate_events(gpu):
+    import torch
+    B = gpu
+    say("empty and degenerate events")
+    # no hits: the matrix is all zero (it is overwritten, not accumulated) and there are no peaks
+    acc = B.new_acc(CFG0)
+    acc.fill_(7)
+    e = torch.zeros(0, dtype=torch.float32, device="cuda")
+    out, nf = B.new_peaks(16)
+    B.ht_fill_peaks(CFG0, e, e, e, acc, out, 16, nf)
+    torch.cuda.synchronize()
+    assert not acc.any() and int(nf.item()) == 0
+    # hits that vote nothing
+    x = np.array([0, 0, np.nan, np.inf, 4, 1e30], np.float32)
+    y = np.array([0, 0, 1, 1, 0, 1e30], np.float32)
+    z = np.array([0, 1, 1, 1, 1, 1], np.float32)
+    gM, gc, gv, gn = gpu_fused(B, CFG0, x, y, z)
+    assert not gM.any() and gn == 0
+    # capacity 0 and truncated capacity still report the total
+    ev = synth.make_event(0, 1)
+    M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
+    assert on >= 3
+    xd, yd, zd = B.hits_to_device(ev.x, ev.y, ev.z)
+    acc = B.new_acc(CFG0)
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    B.ht_fill_peaks(CFG0, xd, yd, zd, acc, None, 0, nf)
+    torch.cuda.synchronize()
+    assert int(nf.item()) == on
+    out, nf = B.new_peaks(2)
+    B.ht_fill_peaks(CFG0, xd, yd, zd, acc, out, 2, nf)
+    torch.cuda.synchronize()
+    c, v, n = B.peaks_to_host(out, nf, 2)
+    assert n == on and np.array_equal(c, oc[:2]) and np.array_equal(v, ov[:2])
+    # threshold above every count
+    spec = synth.GridSpec(4, 16, 64, 64, threshold=10 ** 6)
+    gM, gc, gv, gn = gpu_fused(B, spec, ev.x, ev.y, ev.z)
+    assert gn == 0 and np.array_equal(gM, M)
+
+
+def test_batch_matches_single_events(gpu):
+    B = gpu
+    hits, specs = [], CFG0
+    for e in range(24):
+        ev = synth.make_event(0, 300 + e)
+        k = [ev.n, 0, 1, 17][e % 4]  # uneven sizes, including empty events
+        hits.append((ev.x[:k], ev.y[:k], ev.z[:k]))
+    say("batch of", len(hits), "workload-0 events")
+    res = B.fill_peaks_batch(specs, hits, capacity=64)
+    accs = B.as_u32(res.acc)
+    for i, (x, y, z) in enumerate(hits):
+        M, votes, oc, ov, on = oracle_run(specs, x, y, z)
+        assert np.array_equal(accs[i], M), i
+        c, v, n = res.peaks[i]
+        assert n == on and np.array_equal(c, oc[:64]) and np.array_equal(v, ov[:64]), i
+
+
+def test_batch_of_uneven_paper_sized_events(gpu):
+    """Workload-2 events (1000-8000 hits) on the 4x16x1024x1024 grid, batched, vs the oracle."""
+    B = gpu
+    evs = [synth.make_event(2, e) for e in range(6)]
+    say("batch of 6 workload-2 events, sizes", [e.n for e in evs])
+    res = B.fill_peaks_batch(CFG1, [(e.x, e.y, e.z) for e in evs], capacity=1 << 14)
+    accs = B.as_u32(res.acc)
+    for i, ev in enumerate(evs):
+        M, votes, oc, ov, on = oracle_run(CFG1, ev.x, ev.y, ev.z)
+        assert np.array_equal(accs[i], M), i
+        c, v, n = res.peaks[i]
+        assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov), i
+    del res, accs
+
+
+def serve_all(B, spec, events, opts):
+    import time
+    lib = B.lib()
+    g = B.make_grid(spec)
+    srv = ctypes.c_void_p()
+    B.check(lib.ht_serve_create(ctypes.byref(g), ctypes.byref(opts), ctypes.byref(srv)))
+    try:
+        tickets = []
+        for ev in events:
+            t = ctypes.c_uint64()
+            fp = ctypes.POINTER(ctypes.c_float)
+            while True:
+                rc = lib.ht_serve_submit(srv, ev.x.ctypes.data_as(fp), ev.y.ctypes.data_as(fp),
+                                         ev.z.ctypes.data_as(fp), ev.n, ctypes.byref(t))
+                if rc != B.HT_EAGAIN:
+                    break
+                time.sleep(1e-4)
+            B.check(rc)
+            tickets.append(t.value)
+        results = {}
+        cap = opts.peak_capacity
+        deadline = time.time() + 60
+        while len(results) < len(tickets) and time.time() < deadline:
+            for t in tickets:
+                if t in results:
+                    continue
+                out = (B.Peak * cap)()
+                nf = ctypes.c_int64()
+                tm = B.Timing()
+                rc = lib.ht_serve_poll(srv, t, out, cap, ctypes.byref(nf), ctypes.byref(tm))
+                if rc == B.HT_EAGAIN:
+                    continue
+                B.check(rc)
+                k = min(nf.value, cap)
+                arr = np.frombuffer(out, dtype=np.uint32).reshape(-1, 2)[:k]
+                results[t] = (arr[:, 0].copy(), arr[:, 1].copy(), nf.value, tm)
+            time.sleep(1e-4)
+        assert len(results) == len(tickets), "server did not finish"
+        # a released ticket is unknown
+        nf = ctypes.c_int64()
+        assert lib.ht_serve_poll(srv, tickets[0], None, 0, ctypes.byref(nf), None) == B.HT_EINVAL
+        return [results[t] for t in tickets]
+    finally:
+        lib.ht_serve_destroy(srv)
+
+
+def test_serve_results_equal_alone_and_in_the_mix(gpu):
+    B = gpu
+    evs = [synth.make_event(0, 400 + e) for e in range(30)]
+    one_slot = (4 * CFG0.n_cells + (8 << 20))
+    opts = B.ServeOpts(3 * one_slot, 256, 2000, 4, 2, 64, 0)   # three slots: admission limits
+    say("serve: 30 workload-0 events, 3 slots, 2 streams")
+    mixed = serve_all(B, CFG0, evs, opts)
+    for ev, (c, v, n, tm) in zip(evs, mixed):
+        M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
+        assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
+        assert tm.t_submit <= tm.t_admit <= tm.t_launch <= tm.t_done
+    say("serve: the same events one at a time")
+    for ev, (c, v, n, tm) in zip(evs[:5], mixed[:5]):
+        (c1, v1, n1, _), = serve_all(B, CFG0, [ev], opts)
+        assert n1 == n and np.array_equal(c1, c) and np.array_equal(v1, v)
+
+
+def test_serve_paper_grid(gpu):
+    B = gpu
+    evs = [synth.make_event(3, e) for e in range(4)]
+    say("serve: 4 workload-3 events, sizes", [e.n for e in evs])
+    opts = B.ServeOpts(4 << 30, 1 << 17, 40000, 2, 2, 8, 0)
+    res = serve_all(B, CFG1, evs, opts)
+    for ev, (c, v, n, tm) in zip(evs, res):
+        M, votes, oc, ov, on = oracle_run(CFG1, ev.x, ev.y, ev.z)
+        assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
+
+
+def test_stress_event_full_size(gpu):
+    """One 105600-hit event on the 8x32x2048x2048 grid (4 GiB of counts), bit-exact."""
+    import torch
+    B = gpu
+    ev = synth.make_event(4, 0)
+    say("stress event: workload 4, 105600 hits, 1G cells")
+    xd, yd, zd = B.hits_to_device(ev.x, ev.y, ev.z)
+    acc, gc, gv, gn = B.fill_peaks(CFG4, xd, yd, zd, capacity=1 << 22)
+    torch.cuda.synchronize()
+    M, votes, oc, ov, on = oracle_run(CFG4, ev.x, ev.y, ev.z)
+    say("stress event: oracle done, comparing")
+    gM = B.as_u32(acc)
+    del acc
+    torch.cuda.empty_cache()
+    assert np.array_equal(gM, M)
+    assert gn == on and np.array_equal(gc, oc) and np.array_equal(gv, ov)
