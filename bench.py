@@ -98,6 +98,135 @@ def measure_peaks(B, torch, acc_bytes):
             "buffer_MiB": nbytes >> 20}
 
 
+def bench_batched(B, torch, synth, workload, n_events, reps, capacity):
+    """One ht_fill_peaks_batch call (a captured graph) over n_events events of the workload."""
+    spec = synth.WORKLOADS[workload].grid
+    evs = [synth.make_event(workload, e) for e in range(n_events)]
+    xs = np.concatenate([e.x for e in evs])
+    ys = np.concatenate([e.y for e in evs])
+    zs = np.concatenate([e.z for e in evs])
+    x, y, z = B.hits_to_device(xs, ys, zs)
+    events, off = [], 0
+    for i, e in enumerate(evs):
+        events.append(B.Event(off, e.n, i * capacity, capacity))
+        off += e.n
+    acc = B.new_acc(spec, n_events)
+    out = torch.empty((n_events * capacity, 2), dtype=torch.int32, device="cuda")
+    nf = torch.zeros(n_events, dtype=torch.int64, device="cuda")
+    B.ht_fill_peaks_batch(spec, events, x, y, z, acc, out, nf)
+    torch.cuda.synchronize()
+    votes = int(acc.sum(dtype=torch.int64).item())
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.ht_fill_peaks_batch(spec, events, x, y, z, acc, out, nf)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    res = {"workload": synth.WORKLOADS[workload].name, "events_per_batch": n_events,
+           "hits_mean": round(float(np.mean([e.n for e in evs])), 1),
+           "ms_per_batch": round(dt * 1e3, 3), "events_per_s": round(n_events / dt, 1),
+           "gvotes_per_s": round(votes / dt / 1e9, 2),
+           "hbm_write_GBs": round(4 * spec.n_cells * n_events / dt / 1e9, 1),
+           "peaks_per_event": round(float(nf.float().mean().item()), 1),
+           "max_peaks": int(nf.max().item()), "capacity": capacity}
+    del acc, out, x, y, z
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_served(B, torch, synth, n_pool, n_warm, n_meas, rates, budget_gib, max_batch, n_streams):
+    """Served vs plain on workload 3: the same Poisson arrival traces are replayed through the
+    request loop (continuous batching over streams) and through one-at-a-time ht_fill_peaks."""
+    spec = synth.WORKLOADS[3].grid
+    pool = [synth.make_event(3, e) for e in range(n_pool)]
+    cap = 1 << 17
+    res = {"workload": synth.WORKLOADS[3].name, "pool_events": n_pool,
+           "hits_mean": round(float(np.mean([e.n for e in pool])), 1),
+           "max_batch": max_batch, "n_streams": n_streams, "hbm_budget_GiB": budget_gib}
+
+    # plain: one event at a time, synchronous
+    dev_pool = [B.hits_to_device(e.x, e.y, e.z) for e in pool]
+    acc = B.new_acc(spec)
+    out, nf = B.new_peaks(cap)
+
+    def plain_one(i):
+        x, y, z = dev_pool[i % n_pool]
+        B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+        nf.item()  # waits for the event, as a caller needing its result does
+
+    for i in range(20):
+        plain_one(i)
+    t0 = time.perf_counter()
+    for i in range(200):
+        plain_one(i)
+    plain_rate = 200 / (time.perf_counter() - t0)
+    res["plain_saturation_events_per_s"] = round(plain_rate, 1)
+
+    with B.Server(spec, budget_gib << 30, peak_capacity=cap, max_hits=40000, max_batch=max_batch,
+                  n_streams=n_streams, queue_depth=1024) as srv:
+        def run_trace(arrivals):
+            n = len(arrivals)
+            lat, pending, i, done = [], {}, 0, 0
+            order = []
+            t_base = time.perf_counter()
+            while done < n:
+                now = time.perf_counter() - t_base
+                if i < n and now >= arrivals[i]:
+                    ev = pool[i % n_pool]
+                    t = srv.submit(ev.x, ev.y, ev.z)
+                    if t is not None:
+                        pending[t] = i
+                        order.append(t)
+                        i += 1
+                        continue
+                # collect finished requests (oldest first)
+                progressed = False
+                for t in list(order[:64]):
+                    r = srv.poll(t)
+                    if r is None:
+                        continue
+                    _, _, n_found, tm = r
+                    lat.append((pending.pop(t), tm.t_done - tm.t_submit, tm))
+                    order.remove(t)
+                    done += 1
+                    progressed = True
+                if not progressed and i >= n:
+                    time.sleep(20e-6)
+            t_end = time.perf_counter() - t_base
+            lat.sort()
+            return lat, t_end
+
+        # saturation: everything arrives at once
+        lat, t_end = run_trace(np.zeros(n_warm + n_meas))
+        sat = (n_warm + n_meas) / t_end
+        res["served_saturation_events_per_s"] = round(sat, 1)
+        res["rates"] = []
+        for frac in rates:
+            rate = frac * sat
+            arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, n_warm + n_meas))
+            lat, t_end = run_trace(arr)
+            served = np.array([l for _, l, _ in lat[n_warm:]]) * 1e3
+            # plain replay of the same trace: a FIFO single server
+            t_base = time.perf_counter()
+            plain = []
+            for i, a in enumerate(arr):
+                while time.perf_counter() - t_base < a:
+                    pass
+                plain_one(i)
+                if i >= n_warm:
+                    plain.append((time.perf_counter() - t_base - a) * 1e3)
+            plain = np.array(plain)
+            res["rates"].append({
+                "offered_events_per_s": round(rate, 1), "fraction_of_served_saturation": frac,
+                "served_p50_ms": round(float(np.percentile(served, 50)), 3),
+                "served_p99_ms": round(float(np.percentile(served, 99)), 3),
+                "served_events_per_s": round((n_warm + n_meas) / t_end, 1),
+                "plain_p50_ms": round(float(np.percentile(plain, 50)), 3),
+                "plain_p99_ms": round(float(np.percentile(plain, 99)), 3)})
+    del acc, dev_pool
+    torch.cuda.empty_cache()
+    return res
+
+
 def ctypes_stream(stream):
     import ctypes
     return ctypes.c_void_p(stream.cuda_stream)
@@ -112,6 +241,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="main line only (no extra workloads)")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -145,6 +275,15 @@ def main():
         B.ht_fill_peaks(spec, x, y, z, acc, out[i], cap, nf[i:i + 1], stream)
         h_nf[i:i + 1].copy_(nf[i:i + 1], non_blocking=True)
         h_out[i].copy_(out[i], non_blocking=True)
+
+    # launch shape from the autotuner (every candidate is gated on bit-exact results)
+    tuned = None
+    if not args.no_tune:
+        from paper_1507_03074_amd import tune
+        log("autotuning the launch shape")
+        rep = tune.autotune(spec, [(e.x, e.y, e.z) for e in evs[:4]], reps=30)
+        tuned = {"best": rep["best"], "default_us_per_event": round(rep["default_us_per_event"], 2),
+                 "candidates": len(rep["candidates"])}
 
     # votes per event (the matrix sum; equal to the oracle's count by the parity tests)
     votes = []
@@ -226,6 +365,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_fill", "alg_bytes_per_launch": alg_bytes},
         "peaks_per_event": round(float(np.mean(nfound)), 1),
+        "tuning": B.ht_get_tuning(spec).as_dict(),
+        "autotune": tuned,
     }
     # the plain baseline: zero the matrix, one global atomicAdd per vote (paper-style kernel)
     torch.cuda.synchronize()
@@ -245,6 +386,29 @@ def main():
     line["fill_frac_of_measured_write"] = round(achieved / pk["hbm_write_GBs"], 4)
     line["fill_votes_vs_atomic_roofline"] = round(
         line["fill_gvotes_per_s"] / pk["atomic_rand_Gops"], 3)
+    # plain per-event latency (launch to result on the host), one event at a time
+    lat = []
+    for k in range(100):
+        i = k % args.events
+        x, y, z = dev_hits[i]
+        ts = time.perf_counter()
+        B.ht_fill_peaks(spec, x, y, z, acc, out[i], cap, nf[i:i + 1], stream)
+        h_nf[i:i + 1].copy_(nf[i:i + 1], non_blocking=True)
+        h_out[i].copy_(out[i], non_blocking=True)
+        stream.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+    line["plain_latency_ms"] = {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)}
+    if not args.quick:
+        del acc, out
+        torch.cuda.empty_cache()
+        log("batched workload 2")
+        line["batched"] = bench_batched(B, torch, synth, 2, 100, 5, 1 << 13)
+        log("stress workload 4")
+        line["stress"] = bench_batched(B, torch, synth, 4, 16, 3, 1 << 21)
+        log("served workload 3")
+        line["served"] = bench_served(B, torch, synth, n_pool=128, n_warm=200, n_meas=2000,
+                                      rates=(0.25, 0.5, 0.9), budget_gib=24, max_batch=8,
+                                      n_streams=2)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb, _ = cpu_baseline(spec, workload, args.cpu_seconds)

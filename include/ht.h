@@ -66,7 +66,7 @@ typedef enum ht_status {
   HT_EDEVICE = -5     /* a HIP runtime call failed */
 } ht_status;
 
-/* Binning of the vote matrix. Limits: n_theta >= 1, n_phi >= 3, n_theta*n_phi <= 16384,
+/* Binning of the vote matrix. Limits: n_theta >= 1, n_phi >= 3, n_theta*n_phi <= 4096,
  * 1 <= n_a, n_b <= 2^24, n_theta*n_phi*n_a*n_b <= 2^32, finite ranges with min < max,
  * threshold >= 1. A and B are in the units of the hit coordinates (mm); ranges are half-open. */
 typedef struct ht_grid {
@@ -80,6 +80,25 @@ typedef struct ht_peak {
   uint32_t cell;
   uint32_t votes;
 } ht_peak;
+
+/* Launch shape of the kernels for one grid. Results never depend on it (every shape gives
+ * bit-identical matrices and peak lists); only speed does. Zero (or -1 for nt_store) means the
+ * library's default for that field. */
+typedef struct ht_tuning {
+  int32_t rows;         /* A rows per fill tile: a power of two <= 64 whose rows x n_b uint32
+                           counters fit in 56 KiB of LDS */
+  int32_t group_tiles;  /* tiles per workgroup of the peak search: 16, 32 or 64 */
+  int32_t cand_cap;     /* candidate slots per tile: a power of two in [2, 4096] */
+  int32_t nt_store;     /* 1: the fill writes the matrix with non-temporal stores, 0: ordinary */
+} ht_tuning;
+
+/* ht_set_tuning: use `tuning` for every later call on grids with these dimensions and ranges
+ * (the threshold is ignored); NULL restores the defaults. Host only.
+ * Errors: HT_EINVAL for an invalid grid or a field outside its range. */
+int ht_set_tuning(const ht_grid* grid, const ht_tuning* tuning);
+
+/* ht_get_tuning: the launch shape the library will use for `grid` (defaults filled in). */
+int ht_get_tuning(const ht_grid* grid, ht_tuning* tuning);
 
 /* ht_tables: the bin-rule tables above, computed on the host (no device work). Host pointers:
  * a2[n_a], inv_db[1], phi_cs[2*(2*n_phi)] and th_cs[2*(2*n_theta+1)] as (cos, sin) pairs.
@@ -121,8 +140,10 @@ typedef struct ht_event {
   int64_t peak_capacity;
 } ht_event;
 
-/* ht_fill_peaks_batch: both steps for n_events independent events of uneven sizes, as one
- * captured launch sequence over the whole batch.
+/* ht_fill_peaks_batch: both steps for n_events independent events of uneven sizes. The stages
+ * (prep, fill, peak search) each run as one launch over the whole batch; the sequence, with the
+ * upload of the event descriptors, is captured once per batch shape into a HIP graph and
+ * replayed, so a batch costs one graph launch on the host.
  * events: HOST ht_event[n_events] (copied before the call returns).
  * x, y, z: device float arrays holding all events' hits.
  * acc: device uint32[n_events * cells]; event e's matrix is acc + e*cells, fully overwritten.

@@ -58,13 +58,21 @@ class ServeOpts(ctypes.Structure):
                 ("device", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("group_tiles", ctypes.c_int32),
+                ("cand_cap", ctypes.c_int32), ("nt_store", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Timing(ctypes.Structure):
     _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
                 ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 #: every symbol the public headers declare
-EXPORTS = ["ht_tables", "ht_fill", "ht_peaks", "ht_fill_peaks", "ht_fill_peaks_batch",
+EXPORTS = ["ht_set_tuning", "ht_get_tuning", "ht_tables", "ht_fill", "ht_peaks", "ht_fill_peaks", "ht_fill_peaks_batch",
            "ht_serve_create", "ht_serve_submit", "ht_serve_poll", "ht_serve_destroy",
            "ht_last_error", "ht_debug_hit_values", "ht_fill_atomic", "ht_tiling",
            "ht_profile_enable", "ht_profile_read", "ht_bench_hbm_write", "ht_bench_hbm_read",
@@ -87,6 +95,8 @@ def lib():
     f32p = ctypes.POINTER(ctypes.c_float)
     sig = {
         "ht_tables": ([gp, f32p, f32p, f32p, f32p], ctypes.c_int),
+        "ht_set_tuning": ([gp, ctypes.POINTER(Tuning)], ctypes.c_int),
+        "ht_get_tuning": ([gp, ctypes.POINTER(Tuning)], ctypes.c_int),
         "ht_tiling": ([gp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                        ctypes.POINTER(i32)], ctypes.c_int),
         "ht_fill": ([gp, vp, vp, vp, i64, vp, vp], ctypes.c_int),
@@ -171,6 +181,25 @@ def ht_tables(spec):
     check(lib().ht_tables(ctypes.byref(g), a2.ctypes.data_as(fp), inv.ctypes.data_as(fp),
                           phi.ctypes.data_as(fp), th.ctypes.data_as(fp)))
     return a2, inv[0], phi, th
+
+
+def ht_set_tuning(spec, tuning=None, **fields):
+    """Set the launch shape for a grid (a Tuning, or fields rows/group_tiles/cand_cap/nt_store;
+    unspecified fields keep the default). ht_set_tuning(spec) restores the defaults."""
+    g = make_grid(spec)
+    if tuning is None and not fields:
+        return check(lib().ht_set_tuning(ctypes.byref(g), None))
+    if tuning is None:
+        tuning = Tuning(fields.get("rows", 0), fields.get("group_tiles", 0),
+                        fields.get("cand_cap", 0), fields.get("nt_store", -1))
+    return check(lib().ht_set_tuning(ctypes.byref(g), ctypes.byref(tuning)))
+
+
+def ht_get_tuning(spec) -> Tuning:
+    g = make_grid(spec)
+    t = Tuning()
+    check(lib().ht_get_tuning(ctypes.byref(g), ctypes.byref(t)))
+    return t
 
 
 def ht_tiling(spec):
@@ -325,3 +354,57 @@ def fill_peaks_batch(spec, hits, capacity=1 << 16, acc=None, stream=None, device
         seg = outh[i * capacity: i * capacity + k]
         res.append((seg[:, 0].copy(), seg[:, 1].copy(), int(nfh[i])))
     return BatchResult(acc, res)
+
+
+class Server:
+    """The library's request loop (ht_serve_*) over host numpy hits."""
+
+    def __init__(self, spec, hbm_budget_bytes, peak_capacity=1 << 16, max_hits=40000,
+                 max_batch=16, n_streams=2, queue_depth=256, device=0):
+        self.grid = make_grid(spec)
+        self.opts = ServeOpts(hbm_budget_bytes, peak_capacity, max_hits, max_batch, n_streams,
+                              queue_depth, device)
+        self.cap = peak_capacity
+        self._h = ctypes.c_void_p()
+        check(lib().ht_serve_create(ctypes.byref(self.grid), ctypes.byref(self.opts),
+                                    ctypes.byref(self._h)))
+        self._out = (Peak * peak_capacity)()
+
+    def submit(self, x, y, z):
+        """Returns a ticket, or None when the queue is full (HT_EAGAIN)."""
+        fp = ctypes.POINTER(ctypes.c_float)
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        z = np.ascontiguousarray(z, np.float32)
+        t = ctypes.c_uint64()
+        rc = lib().ht_serve_submit(self._h, x.ctypes.data_as(fp), y.ctypes.data_as(fp),
+                                   z.ctypes.data_as(fp), x.size, ctypes.byref(t))
+        if rc == HT_EAGAIN:
+            return None
+        check(rc)
+        return t.value
+
+    def poll(self, ticket):
+        """None while in flight; else (cells, votes, n_found, Timing)."""
+        nf = ctypes.c_int64()
+        tm = Timing()
+        rc = lib().ht_serve_poll(self._h, ticket, self._out, self.cap, ctypes.byref(nf),
+                                 ctypes.byref(tm))
+        if rc == HT_EAGAIN:
+            return None
+        if rc not in (HT_OK, HT_EOVERFLOW):
+            check(rc)
+        k = min(nf.value, self.cap)
+        arr = np.frombuffer(self._out, dtype=np.uint32).reshape(-1, 2)[:k]
+        return arr[:, 0].copy(), arr[:, 1].copy(), nf.value, tm
+
+    def close(self):
+        if self._h:
+            lib().ht_serve_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -98,12 +98,27 @@ static int env_int(const char* name, int def)
 
 // Largest power-of-two row count (<= 64) whose u32 tile fits the LDS budget; the candidate
 // slots per tile scale with the tile (1/32 of its cells, 64..1024).
+// Per-grid launch shapes set through ht_set_tuning (keyed by dimensions and ranges).
+typedef std::tuple<int32_t, int32_t, int32_t, int32_t, uint32_t, uint32_t, uint32_t, uint32_t> TuneKey;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, ht_tuning> g_tune;
+
+static uint32_t fbits(float f);
+
+static TuneKey tune_key(const ht_grid& g)
+{
+  return TuneKey{g.n_theta, g.n_phi, g.n_a, g.n_b, fbits(g.a_min), fbits(g.a_max), fbits(g.b_min),
+                 fbits(g.b_max)};
+}
+
+static const int64_t kLdsTileMax = 65536 - 8192;  // bytes of an LDS tile (room for candidates)
+
 Tiling choose_tiling(const ht_grid& g)
 {
   Tiling t;
   const int64_t row_bytes = (int64_t)g.n_b * 4;
   const int64_t budget = env_int("HT_FILL_LDS_BYTES", 32768);
-  const int64_t lds_max = 65536 - 8192;  // room for the candidate list
+  const int64_t lds_max = kLdsTileMax;
   t.lds_fill = row_bytes <= lds_max ? 1 : 0;
   int rows = 1;
   if (t.lds_fill) {
@@ -134,7 +149,43 @@ Tiling choose_tiling(const ht_grid& g)
   if (forced_gt == 16 || forced_gt == 32 || forced_gt == 64) gt = forced_gt;
   t.group_tiles = gt;
   t.nt_store = env_int("HT_FILL_NT", 0) ? 1 : 0;
+  ht_tuning tu;
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(g));
+    if (it != g_tune.end()) {
+      tu = it->second;
+      have = true;
+    }
+  }
+  if (have) {
+    if (tu.rows > 0 && t.lds_fill) t.rows = tu.rows;
+    if (tu.group_tiles > 0) t.group_tiles = tu.group_tiles;
+    if (tu.cand_cap > 0) t.cand_cap = tu.cand_cap;
+    if (tu.nt_store >= 0) t.nt_store = tu.nt_store;
+    t.tiles_per_slab = (g.n_a + t.rows - 1) / t.rows;
+    t.n_tiles = g.n_theta * g.n_phi * t.tiles_per_slab;
+  }
   return t;
+}
+
+int check_tuning(const ht_grid& g, const ht_tuning& tu)
+{
+  auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+  if (tu.rows < 0 || (tu.rows > 0 && (!pow2(tu.rows) || tu.rows > 64 ||
+                                      (int64_t)tu.rows * g.n_b * 4 > kLdsTileMax)))
+    return fail(HT_EINVAL, "tuning.rows must be a power of two <= 64 with rows*n_b*4 <= %lld",
+                (long long)kLdsTileMax);
+  if ((int64_t)g.n_theta * g.n_phi * ((g.n_a + std::max(tu.rows, 1) - 1) / std::max(tu.rows, 1)) >
+      0x7fffffffLL)
+    return fail(HT_EINVAL, "tuning.rows gives too many tiles");
+  if (tu.group_tiles != 0 && tu.group_tiles != 16 && tu.group_tiles != 32 && tu.group_tiles != 64)
+    return fail(HT_EINVAL, "tuning.group_tiles must be 16, 32 or 64");
+  if (tu.cand_cap < 0 || (tu.cand_cap > 0 && (!pow2(tu.cand_cap) || tu.cand_cap < 2 || tu.cand_cap > 4096)))
+    return fail(HT_EINVAL, "tuning.cand_cap must be a power of two in [2, 4096]");
+  if (tu.nt_store < -1 || tu.nt_store > 1) return fail(HT_EINVAL, "tuning.nt_store must be -1, 0 or 1");
+  return HT_OK;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -261,6 +312,12 @@ struct Workspace {
   EvDesc* d_ev = nullptr;
   int ev_cap = 0;
   hipEvent_t ev_copied = nullptr;
+  hipStream_t capture = nullptr;  // private stream used only to capture batch graphs
+  struct Graph {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
 };
 
 static std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
@@ -355,6 +412,8 @@ static bool g_prof_on = false;
 static std::vector<ProfRec> g_prof;
 static std::vector<hipEvent_t> g_prof_pool;
 
+static thread_local bool t_capturing = false;
+
 static hipEvent_t prof_event()
 {
   if (!g_prof_pool.empty()) {
@@ -374,7 +433,7 @@ struct StageTimer {
   StageTimer(const char* n, hipStream_t st) : name(n), s(st)
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || t_capturing) return;
     a = prof_event();
     if (a) (void)hipEventRecord(a, s);
   }
@@ -597,10 +656,94 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
     d.cap = ev.peak_capacity;
     d.n_found = n_found + i;
   }
-  hipError_t e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, p.s);
-  if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(descriptors)");
+  // prep grids are sized for a power-of-two bucket of workgroups, so batches of one size share
+  // a graph (workgroups past an event's hits return at once)
+  int64_t blocks = 1;
+  while (blocks * 256 < max_hits) blocks *= 2;
+  const int64_t max_hits_b = max_hits > 0 ? blocks * 256 : 0;
+  hipError_t e;
+  if (env_int("HT_BATCH_GRAPH", 1) == 0) {
+    e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, p.s);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(descriptors)");
+    if ((e = hipEventRecord(w->ev_copied, p.s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
+    return launch_batch(p.g, w->d_ev, n_events, max_hits_b, p.s);
+  }
+  // graph key: everything the captured launches depend on besides the descriptor contents
+  std::vector<unsigned char> key(sizeof(DevGrid) + 3 * sizeof(int64_t) + 2 * sizeof(void*));
+  {
+    unsigned char* q = key.data();
+    std::memcpy(q, &p.g, sizeof(DevGrid));
+    q += sizeof(DevGrid);
+    const int64_t ints[3] = {n_events, max_hits_b, p.dev};
+    std::memcpy(q, ints, sizeof(ints));
+    q += sizeof(ints);
+    const void* ptrs[2] = {w->d_ev, w->h_ev};
+    std::memcpy(q, ptrs, sizeof(ptrs));
+  }
+  hipGraphExec_t exec = nullptr;
+  for (auto& gr : w->graphs)
+    if (gr.key == key) exec = gr.exec;
+  if (!exec) {
+    if (!w->capture && (e = hipStreamCreateWithFlags(&w->capture, hipStreamNonBlocking)) != hipSuccess)
+      return fail_hip(e, "hipStreamCreate(capture)");
+    // the capture stream must not start before earlier work on the caller's stream is done
+    // with the descriptor staging; capturing records work without running it
+    if ((e = hipStreamBeginCapture(w->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return fail_hip(e, "hipStreamBeginCapture");
+    t_capturing = true;
+    e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, w->capture);
+    int lrc = e == hipSuccess ? launch_batch(p.g, w->d_ev, n_events, max_hits_b, w->capture) : HT_EDEVICE;
+    t_capturing = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(w->capture, &graph);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(descriptors, capture)");
+    if (lrc != HT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return lrc;
+    }
+    if (e2 != hipSuccess) return fail_hip(e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+    if (w->graphs.size() >= 16) {
+      (void)hipGraphExecDestroy(w->graphs.front().exec);
+      w->graphs.erase(w->graphs.begin());
+    }
+    w->graphs.push_back({key, exec});
+  }
+  {
+    StageTimer t("batch", p.s);
+    if ((e = hipGraphLaunch(exec, p.s)) != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+  }
   if ((e = hipEventRecord(w->ev_copied, p.s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
-  return launch_batch(p.g, w->d_ev, n_events, max_hits, p.s);
+  return HT_OK;
+}
+
+int ht_set_tuning(const ht_grid* grid, const ht_tuning* tuning)
+{
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!tuning) {
+    g_tune.erase(tune_key(*grid));
+    return HT_OK;
+  }
+  if ((rc = check_tuning(*grid, *tuning))) return rc;
+  g_tune[tune_key(*grid)] = *tuning;
+  return HT_OK;
+}
+
+int ht_get_tuning(const ht_grid* grid, ht_tuning* tuning)
+{
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (!tuning) return fail(HT_EINVAL, "tuning is NULL");
+  Tiling t = choose_tiling(*grid);
+  tuning->rows = t.rows;
+  tuning->group_tiles = t.group_tiles;
+  tuning->cand_cap = t.cand_cap;
+  tuning->nt_store = t.nt_store;
+  return HT_OK;
 }
 
 int ht_debug_hit_values(const ht_grid* grid, const float* x, const float* y, const float* z,

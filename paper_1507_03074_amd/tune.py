@@ -1,0 +1,120 @@
+"""Autotuner for the launch shape of the fill and peak kernels (ht_set_tuning).
+
+For one grid and a few representative events it times every candidate shape (A rows per fill
+tile, tiles per peak workgroup, store kind of the matrix flush), keeps only candidates whose vote
+matrices and peak lists are bit-identical to those of the default shape, and applies the
+fastest. Results are cached in a JSON file keyed by GPU architecture and grid.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+
+import numpy as np
+
+from . import binding as B
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def arch_name() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def grid_key(spec) -> str:
+    g = B.make_grid(spec)
+    return "%dx%dx%dx%d[%g,%g)x[%g,%g)" % (g.n_theta, g.n_phi, g.n_a, g.n_b, g.a_min, g.a_max,
+                                          g.b_min, g.b_max)
+
+
+def candidates(spec):
+    g = B.make_grid(spec)
+    rows = [r for r in (1, 2, 4, 8, 16, 32, 64) if r * g.n_b * 4 <= 57344 and r <= max(1, g.n_a)]
+    rows = rows[-3:] if len(rows) > 3 else rows
+    for r, gt, nt in itertools.product(rows, (16, 32, 64), (0, 1)):
+        yield B.Tuning(r, gt, 0, nt)
+
+
+def _run(spec, hits, acc, out, nf, cap, reps):
+    import torch
+    for x, y, z in hits:
+        B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        x, y, z = hits[k % len(hits)]
+        B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool = True):
+    """Time every candidate on `events` (host (x, y, z) tuples); returns a report dict."""
+    import torch
+    hits = [B.hits_to_device(*e) for e in events]
+    acc = B.new_acc(spec)
+    out, nf = B.new_peaks(capacity)
+    B.ht_set_tuning(spec)
+    # reference results: default shape
+    ref = []
+    for x, y, z in hits:
+        B.ht_fill_peaks(spec, x, y, z, acc, out, capacity, nf)
+        torch.cuda.synchronize()
+        ref.append((acc.clone(), B.peaks_to_host(out, nf, capacity)))
+    t_default = _run(spec, hits, acc, out, nf, capacity, reps)
+    results = []
+    for cand in candidates(spec):
+        try:
+            B.ht_set_tuning(spec, cand)
+        except B.HTError:
+            continue
+        exact = True
+        for (x, y, z), (racc, rpk) in zip(hits, ref):
+            B.ht_fill_peaks(spec, x, y, z, acc, out, capacity, nf)
+            torch.cuda.synchronize()
+            pk = B.peaks_to_host(out, nf, capacity)
+            if not (torch.equal(acc, racc) and pk[2] == rpk[2] and np.array_equal(pk[0], rpk[0])
+                    and np.array_equal(pk[1], rpk[1])):
+                exact = False
+                break
+        t = _run(spec, hits, acc, out, nf, capacity, reps) if exact else None
+        results.append({"tuning": cand.as_dict(), "us_per_event": None if t is None else t * 1e6,
+                        "bit_exact": exact})
+    B.ht_set_tuning(spec)
+    ok = [r for r in results if r["bit_exact"]]
+    best = min(ok, key=lambda r: r["us_per_event"]) if ok else None
+    if apply and best:
+        B.ht_set_tuning(spec, B.Tuning(**best["tuning"]))
+    del acc, out, ref
+    torch.cuda.empty_cache()
+    return {"grid": grid_key(spec), "arch": arch_name(), "default_us_per_event": t_default * 1e6,
+            "best": best, "candidates": results}
+
+
+def save(report, path: str = DEFAULT_CACHE):
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            cache = json.load(fh)
+    if report.get("best"):
+        cache.setdefault(report["arch"], {})[report["grid"]] = report["best"]["tuning"]
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def load(spec, path: str = DEFAULT_CACHE) -> bool:
+    """Apply the cached shape for this GPU and grid, if there is one."""
+    if not os.path.exists(path):
+        return False
+    with open(path) as fh:
+        cache = json.load(fh)
+    t = cache.get(arch_name(), {}).get(grid_key(spec))
+    if not t:
+        return False
+    B.ht_set_tuning(spec, B.Tuning(**t))
+    return True

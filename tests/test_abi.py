@@ -119,3 +119,29 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libht.so")
     with pytest.raises(B.HTError):
         B.lib()
+
+
+def test_tuning_validated_and_applied_on_host(lib):
+    spec = synth.GridSpec(4, 16, 1024, 1024, threshold=9)
+    default = B.ht_get_tuning(spec).as_dict()
+    assert default["rows"] == B.ht_tiling(spec)["rows"]
+    for bad in [dict(rows=3), dict(rows=128), dict(rows=32),  # 32 x 1024 x 4 B exceeds the LDS tile
+                dict(group_tiles=8), dict(cand_cap=3), dict(cand_cap=8192), dict(nt_store=2)]:
+        with pytest.raises(B.HTError):
+            B.ht_set_tuning(spec, **bad)
+        assert B.ht_get_tuning(spec).as_dict() == default
+    B.ht_set_tuning(spec, rows=4, group_tiles=32, cand_cap=128, nt_store=1)
+    try:
+        got = B.ht_get_tuning(spec).as_dict()
+        assert got == {"rows": 4, "group_tiles": 32, "cand_cap": 128, "nt_store": 1}
+        # the threshold is not part of the key
+        other = synth.GridSpec(4, 16, 1024, 1024, threshold=3)
+        assert B.ht_get_tuning(other).as_dict() == got
+        assert B.ht_tiling(spec)["n_tiles"] == 64 * 256
+        # unspecified fields keep their defaults
+        B.ht_set_tuning(spec, rows=2)
+        got = B.ht_get_tuning(spec).as_dict()
+        assert got["rows"] == 2 and got["group_tiles"] == default["group_tiles"]
+    finally:
+        B.ht_set_tuning(spec)
+    assert B.ht_get_tuning(spec).as_dict() == default

@@ -39,7 +39,7 @@ def gpu():
 
 @pytest.fixture()
 def env_tiling():
-    keys = ("HT_FILL_ROWS", "HT_CAND_CAP", "HT_FILL_LDS_BYTES")
+    keys = ("HT_FILL_ROWS", "HT_CAND_CAP", "HT_FILL_LDS_BYTES", "HT_BATCH_GRAPH")
     saved = {k: os.environ.get(k) for k in keys}
     yield
     for k, v in saved.items():
@@ -190,32 +190,55 @@ def test_ragged_grids_bit_exact(gpu, spec):
 
 
 @pytest.mark.parametrize("rows", [1, 2, 4, 8, 16, 32, 64])
-def test_every_tile_shape_bit_exact(gpu, env_tiling, rows):
+def test_every_tile_shape_bit_exact(gpu, rows):
+    """Every launch shape the tuner can pick gives the same bits."""
     B = gpu
-    os.environ["HT_FILL_ROWS"] = str(rows)
     for spec, ev in ((CFG0, synth.make_event(0, 3)), (synth.GridSpec(4, 16, 100, 40, threshold=4),
                                                        synth.make_event(0, 4))):
-        say("tile rows", rows, "grid", spec.shape)
-        gM, gc, gv, gn = gpu_fused(B, spec, ev.x, ev.y, ev.z)
         M, votes, oc, ov, on = oracle_run(spec, ev.x, ev.y, ev.z)
-        assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "rows %d" % rows)
+        for gt, nt in ((16, 0), (64, 1)):
+            say("tile rows", rows, "group tiles", gt, "nt", nt, "grid", spec.shape)
+            B.ht_set_tuning(spec, rows=rows, group_tiles=gt, nt_store=nt)
+            try:
+                gM, gc, gv, gn = gpu_fused(B, spec, ev.x, ev.y, ev.z)
+            finally:
+                B.ht_set_tuning(spec)
+            assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "rows %d" % rows)
 
 
-def test_candidate_overflow_uses_dense_path(gpu, env_tiling):
+def test_paper_grid_tile_shapes_bit_exact(gpu):
+    B = gpu
+    ev = synth.make_event(1, 7)
+    M, votes, oc, ov, on = oracle_run(CFG1, ev.x, ev.y, ev.z)
+    for rows in (1, 2, 4, 8):
+        for nt in (0, 1):
+            say("workload 1, rows", rows, "nt", nt)
+            B.ht_set_tuning(CFG1, rows=rows, nt_store=nt, group_tiles=32)
+            try:
+                gM, gc, gv, gn = gpu_fused(B, CFG1, ev.x, ev.y, ev.z)
+            finally:
+                B.ht_set_tuning(CFG1)
+            assert_same(CFG1, gM, gc, gv, gn, M, oc, ov, on, "rows %d nt %d" % (rows, nt))
+
+
+def test_candidate_overflow_uses_dense_path(gpu):
     """With 2 candidate slots per tile, crowded tiles overflow and are searched densely; the
     results must not change."""
+    import torch
     B = gpu
-    os.environ["HT_CAND_CAP"] = "2"
-    for e in (0, 1, 2):
-        say("candidate overflow, workload 0 event", e)
-        ev = synth.make_event(0, e)
-        gM, gc, gv, gn = gpu_fused(B, CFG0, ev.x, ev.y, ev.z)
-        M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
-        assert_same(CFG0, gM, gc, gv, gn, M, oc, ov, on)
-        import torch
-        acc = torch.from_numpy(M.view(np.int32).copy()).cuda()
-        c, v, n = B.peaks(CFG0, acc)
-        assert n == on and np.array_equal(c, oc)
+    B.ht_set_tuning(CFG0, cand_cap=2)
+    try:
+        for e in (0, 1, 2):
+            say("candidate overflow, workload 0 event", e)
+            ev = synth.make_event(0, e)
+            gM, gc, gv, gn = gpu_fused(B, CFG0, ev.x, ev.y, ev.z)
+            M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
+            assert_same(CFG0, gM, gc, gv, gn, M, oc, ov, on)
+            acc = torch.from_numpy(M.view(np.int32).copy()).cuda()
+            c, v, n = B.peaks(CFG0, acc)
+            assert n == on and np.array_equal(c, oc)
+    finally:
+        B.ht_set_tuning(CFG0)
 
 
 def test_paper_sized_events_bit_exact(gpu):
@@ -284,6 +307,34 @@ def test_batch_matches_single_events(gpu):
         assert np.array_equal(accs[i], M), i
         c, v, n = res.peaks[i]
         assert n == on and np.array_equal(c, oc[:64]) and np.array_equal(v, ov[:64]), i
+
+
+def test_batch_graph_replays_match_eager(gpu, env_tiling):
+    """The batch runs as a captured HIP graph. Replay it on several batches of one shape, with
+    host work and synchronisation in between, and compare each replay with the direct launches
+    of the same batch and with the oracle."""
+    import torch
+    B = gpu
+    for rep in range(4):
+        hits = []
+        for e in range(12):
+            ev = synth.make_event(0, 500 + 12 * rep + e)
+            k = ev.n - (e % 3) * 40
+            hits.append((ev.x[:k], ev.y[:k], ev.z[:k]))
+        say("graph replay", rep)
+        os.environ["HT_BATCH_GRAPH"] = "1"
+        g_res = B.fill_peaks_batch(CFG0, hits, capacity=64)
+        os.environ["HT_BATCH_GRAPH"] = "0"
+        e_res = B.fill_peaks_batch(CFG0, hits, capacity=64)
+        os.environ.pop("HT_BATCH_GRAPH")
+        torch.cuda.synchronize()
+        assert np.array_equal(B.as_u32(g_res.acc), B.as_u32(e_res.acc))
+        for i, (x, y, z) in enumerate(hits):
+            M, votes, oc, ov, on = oracle_run(CFG0, x, y, z)
+            assert np.array_equal(B.as_u32(g_res.acc)[i], M)
+            for res in (g_res, e_res):
+                c, v, n = res.peaks[i]
+                assert n == on and np.array_equal(c, oc[:64]) and np.array_equal(v, ov[:64])
 
 
 def test_batch_of_uneven_paper_sized_events(gpu):
@@ -391,3 +442,27 @@ def test_stress_event_full_size(gpu):
     torch.cuda.empty_cache()
     assert np.array_equal(gM, M)
     assert gn == on and np.array_equal(gc, oc) and np.array_equal(gv, ov)
+
+
+def test_autotuner_keeps_results_and_caches(gpu, tmp_path):
+    from paper_1507_03074_amd import tune
+    B = gpu
+    evs = [synth.make_event(0, 600 + e) for e in range(2)]
+    say("autotune workload-0 grid")
+    rep = tune.autotune(CFG0, [(e.x, e.y, e.z) for e in evs], reps=3)
+    assert rep["best"] is not None and rep["best"]["bit_exact"]
+    assert all(c["bit_exact"] for c in rep["candidates"])
+    try:
+        applied = B.ht_get_tuning(CFG0).as_dict()
+        assert applied == rep["best"]["tuning"]
+        path = str(tmp_path / "cache.json")
+        tune.save(rep, path)
+        B.ht_set_tuning(CFG0)
+        assert tune.load(CFG0, path)
+        assert B.ht_get_tuning(CFG0).as_dict() == rep["best"]["tuning"]
+        ev = synth.make_event(0, 610)
+        gM, gc, gv, gn = gpu_fused(B, CFG0, ev.x, ev.y, ev.z)
+        M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
+        assert_same(CFG0, gM, gc, gv, gn, M, oc, ov, on)
+    finally:
+        B.ht_set_tuning(CFG0)
