@@ -227,6 +227,72 @@ def bench_served(B, torch, synth, n_pool, n_warm, n_meas, rates, budget_gib, max
     return res
 
 
+def bench_transfers(B, torch, synth, spec, sizes=(500, 1000, 2000, 4000, 8000), reps=20):
+    """Where the paper's time went (its Fig. 3g: device-to-host transfer dominated): copy costs
+    of the full vote matrix versus the peak list only, hit uploads, and a hit-count sweep of the
+    stage times."""
+    stream = torch.cuda.current_stream()
+    acc = B.new_acc(spec)
+    cap = 1 << 14
+    out, nf = B.new_peaks(cap)
+    res = {}
+
+    def tcopy(dst, src, n=5):
+        dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    host_pinned = torch.empty(acc.shape, dtype=torch.int32, pin_memory=True)
+    host_page = torch.empty(acc.shape, dtype=torch.int32)
+    res["matrix_d2h_pinned_ms"] = round(tcopy(host_pinned, acc) * 1e3, 3)
+    res["matrix_d2h_pageable_ms"] = round(tcopy(host_page, acc, 2) * 1e3, 3)
+    res["matrix_bytes"] = acc.numel() * 4
+    del host_pinned, host_page
+    ev = synth.make_event(1, 0)
+    x, y, z = B.hits_to_device(ev.x, ev.y, ev.z)
+    B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+    n = int(nf.item())
+    hp = torch.empty((cap, 2), dtype=torch.int32, pin_memory=True)
+    res["peaks_d2h_us"] = round(tcopy(hp[:n], out[:n], 50) * 1e6, 2)
+    res["peaks_bytes"] = n * 8
+    hx = torch.from_numpy(np.ascontiguousarray(ev.x))
+    hxp = hx.pin_memory()
+    res["hits_h2d_pinned_us"] = round(3 * tcopy(x, hxp, 50) * 1e6, 2)
+    res["hits_h2d_pageable_us"] = round(3 * tcopy(x, hx, 50) * 1e6, 2)
+    sweep = []
+    for nh in sizes:
+        nt, nn = synth.hits_split(nh)
+        e = synth.make_hits(np.random.default_rng(9000 + nh), nt, nn)
+        xd, yd, zd = B.hits_to_device(e.x, e.y, e.z)
+        for _ in range(3):
+            B.ht_fill_peaks(spec, xd, yd, zd, acc, out, cap, nf)
+        torch.cuda.synchronize()
+        for st in ("prep", "fill", "peaks"):
+            B.ht_profile_read(st, reset=True)
+        B.ht_profile_enable(True)
+        for _ in range(reps):
+            B.ht_fill_peaks(spec, xd, yd, zd, acc, out, cap, nf)
+        torch.cuda.synchronize()
+        B.ht_profile_enable(False)
+        row = {"hits": nh}
+        for st in ("prep", "fill", "peaks"):
+            ms, c = B.ht_profile_read(st)
+            row[st + "_us"] = round(ms / max(c, 1) * 1e3, 2)
+        B.ht_profile_read("fill", reset=True)
+        k = int(nf.item())
+        row["peaks"] = k
+        row["peaks_d2h_us"] = round(tcopy(hp[:max(k, 1)], out[:max(k, 1)], 20) * 1e6, 2)
+        sweep.append(row)
+    res["hit_sweep"] = sweep
+    del acc, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def ctypes_stream(stream):
     import ctypes
     return ctypes.c_void_p(stream.cuda_stream)
@@ -270,11 +336,10 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(k):
+        # the peak kernel writes the peak list and its count straight into pinned host memory
         i = k % args.events
         x, y, z = dev_hits[i]
-        B.ht_fill_peaks(spec, x, y, z, acc, out[i], cap, nf[i:i + 1], stream)
-        h_nf[i:i + 1].copy_(nf[i:i + 1], non_blocking=True)
-        h_out[i].copy_(out[i], non_blocking=True)
+        B.ht_fill_peaks(spec, x, y, z, acc, h_out[i], cap, h_nf[i:i + 1], stream)
 
     # launch shape from the autotuner (every candidate is gated on bit-exact results)
     tuned = None
@@ -352,7 +417,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": synth.WORKLOADS[workload].name, "hits_per_event": 5000,
                    "grid": list(spec.shape), "threshold": spec.threshold,
-                   "path": "ht_fill_peaks (fused) + peak list D2H", "tile_rows": t["rows"],
+                   "path": "ht_fill_peaks (fused), peak list written to pinned host memory", "tile_rows": t["rows"],
                    "resident_events": args.events},
         "gvotes_per_s": round(total_votes / elapsed / 1e9, 3),
         "votes_per_event": round(float(np.mean(votes)), 1),
@@ -386,15 +451,31 @@ def main():
     line["fill_frac_of_measured_write"] = round(achieved / pk["hbm_write_GBs"], 4)
     line["fill_votes_vs_atomic_roofline"] = round(
         line["fill_gvotes_per_s"] / pk["atomic_rand_Gops"], 3)
+    # physics check of the peak lists against the generator's truth (Fig. 1 analogue)
+    from paper_1507_03074_amd import physics
+    phys = []
+    for i in range(min(args.events, 8)):
+        x, y, z = dev_hits[i]
+        B.ht_fill_peaks(spec, x, y, z, acc, out[i], cap, nf[i:i + 1], stream)
+        tr = B.tracks_to_host(B.ht_readout(spec, out[i], nf[i:i + 1], cap), nf[i:i + 1], cap)
+        phys.append(physics.evaluate(spec, tr, evs[i]))
+    line["physics"] = {
+        "events": len(phys),
+        "efficiency": round(sum(p["found"] for p in phys) / max(1, sum(p["in_acceptance"] for p in phys)), 4),
+        "fake_rate": round(sum(p["unmatched_peaks"] for p in phys) / max(1, sum(p["peaks"] for p in phys)), 4),
+        "rho_resolution_ht": round(float(np.mean([p["rho_resolution_ht"] for p in phys])), 5),
+        "phi_resolution_ht_mrad": round(1e3 * float(np.mean([p["phi_resolution_ht"] for p in phys])), 3),
+        "rho_resolution_lsq_fit": round(float(np.mean([p["rho_resolution_fit"] for p in phys])), 6),
+        "phi_resolution_lsq_fit_mrad": round(1e3 * float(np.mean([p["phi_resolution_fit"] for p in phys])), 4),
+        "tracks_in_acceptance_per_event": round(float(np.mean([p["in_acceptance"] for p in phys])), 1)}
+
     # plain per-event latency (launch to result on the host), one event at a time
     lat = []
     for k in range(100):
         i = k % args.events
         x, y, z = dev_hits[i]
         ts = time.perf_counter()
-        B.ht_fill_peaks(spec, x, y, z, acc, out[i], cap, nf[i:i + 1], stream)
-        h_nf[i:i + 1].copy_(nf[i:i + 1], non_blocking=True)
-        h_out[i].copy_(out[i], non_blocking=True)
+        B.ht_fill_peaks(spec, x, y, z, acc, h_out[i], cap, h_nf[i:i + 1], stream)
         stream.synchronize()
         lat.append((time.perf_counter() - ts) * 1e3)
     line["plain_latency_ms"] = {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)}
@@ -405,6 +486,8 @@ def main():
         line["batched"] = bench_batched(B, torch, synth, 2, 100, 5, 1 << 13)
         log("stress workload 4")
         line["stress"] = bench_batched(B, torch, synth, 4, 16, 3, 1 << 21)
+        log("transfer study")
+        line["transfers"] = bench_transfers(B, torch, synth, spec)
         log("served workload 3")
         line["served"] = bench_served(B, torch, synth, n_pool=128, n_warm=200, n_meas=2000,
                                       rates=(0.25, 0.5, 0.9), budget_gib=24, max_batch=8,

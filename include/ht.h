@@ -44,6 +44,9 @@
  *   - "device pointer" arguments are GPU memory owned by the caller (e.g. torch tensors); the
  *     library never frees them. Work is enqueued on `stream` (a hipStream_t, NULL for the null
  *     stream) and is asynchronous unless stated otherwise.
+ *   - the peak outputs (out, n_found, and ht_readout's arrays) may also be pinned host memory
+ *     mapped into the device (hipHostMalloc): the kernels then write the results straight to
+ *     the host, with no copy afterwards. Any other host pointer there is rejected (HT_EINVAL).
  *   - device failures are reported as HT_EDEVICE by the call that observes them.
  *   - the library keeps per-(device, stream) scratch memory; calls on one stream are ordered,
  *     calls on different streams never share scratch.
@@ -130,6 +133,26 @@ int ht_peaks(const ht_grid* grid, const uint32_t* acc, ht_peak* out, int64_t cap
 int ht_fill_peaks(const ht_grid* grid, const float* x, const float* y, const float* z,
                   int64_t n_hits, uint32_t* acc, ht_peak* out, int64_t capacity,
                   int64_t* n_found, void* stream);
+
+/* Track parameters of one peak (paper section 2: the centre (A, B) of the circle gives
+ * rho = sqrt(A^2 + B^2) and phi = tan^-1(B/A)). */
+typedef struct ht_track {
+  uint32_t cell, votes;   /* the peak */
+  int32_t t, p, a, b;     /* its theta, phi, A and B bin indices */
+  float A, B;             /* centres of its A and B bins (mm): the circle centre */
+  float rho;              /* sqrt(A^2 + B^2): the circle radius, proportional to p_T */
+  float phi;              /* atan2(B, A) in [0, 2 pi): azimuth of the centre */
+  float theta;            /* centre of its theta cell (rad) */
+} ht_track;
+
+/* ht_readout: track parameters of a peak list (NEXT to the peak search, paper section 2).
+ * peaks: device ht_peak[capacity] as written by ht_peaks / ht_fill_peaks; n_found: device int64,
+ * the count written by that call (entries past min(*n_found, capacity) are not read);
+ * tracks: device ht_track[capacity], entry i filled for i < min(*n_found, capacity).
+ * Values are computed in double and rounded once to float. Asynchronous on stream.
+ * Errors: HT_EINVAL, HT_EDEVICE. */
+int ht_readout(const ht_grid* grid, const ht_peak* peaks, const int64_t* n_found, int64_t capacity,
+               ht_track* tracks, void* stream);
 
 /* One event of a batch: its hits are x/y/z[hit_offset, hit_offset + n_hits) of the concatenated
  * arrays; its peaks go to out[peak_offset, peak_offset + peak_capacity). */

@@ -287,3 +287,44 @@ int64_t oracle_peaks(const oracle_grid* g, const uint32_t* M, uint32_t* out_cell
   }
   return found;
 }
+
+/* Track parameters of peaks (paper section 2: the circle centre (A, B) of a maximum gives
+ * rho = sqrt(A^2 + B^2) and the azimuth phi = tan^-1(B/A) of the centre, taken in [0, 2 pi)
+ * with atan2 so that the quadrant is kept). A and B are the centres of the peak's A and B bins,
+ * A = A2[a] / 2 and B = b_min + (b + 1/2) (b_max - b_min) / n_b; theta is the centre of the
+ * peak's theta cell. Computed in double. out[9*i] = {t, p, a, b, A, B, rho, phi, theta} with the
+ * four indices as doubles; n_out = n. */
+int oracle_readout(const oracle_grid* g, const uint32_t* cells, int64_t n, double* out)
+{
+  if (oracle_check_grid(g) != ORACLE_OK || n < 0) return ORACLE_EINVAL;
+  float* a2 = (float*)malloc(sizeof(float) * (size_t)g->n_a);
+  float* phi_cs = (float*)malloc(sizeof(float) * 4 * (size_t)g->n_phi);
+  float* th_cs = (float*)malloc(sizeof(float) * (4 * (size_t)g->n_theta + 2));
+  float inv_db;
+  oracle_tables(g, a2, &inv_db, phi_cs, th_cs);
+  const int64_t n_b = g->n_b, n_a = g->n_a, n_p = g->n_phi;
+  const double db = ((double)g->b_max - (double)g->b_min) / (double)g->n_b;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t c = cells[i];
+    const int64_t b = c % n_b, a = (c / n_b) % n_a, p = (c / (n_b * n_a)) % n_p;
+    const int64_t t = c / (n_b * n_a * n_p);
+    const double A = 0.5 * (double)a2[a];
+    const double B = (double)g->b_min + ((double)b + 0.5) * db;
+    double phi = atan2(B, A);
+    if (phi < 0.0) phi += 2.0 * kPi;
+    double* o = out + 9 * i;
+    o[0] = (double)t;
+    o[1] = (double)p;
+    o[2] = (double)a;
+    o[3] = (double)b;
+    o[4] = A;
+    o[5] = B;
+    o[6] = sqrt(A * A + B * B);
+    o[7] = phi;
+    o[8] = ((double)t + 0.5) * kPi / (double)g->n_theta;
+  }
+  free(a2);
+  free(phi_cs);
+  free(th_cs);
+  return ORACLE_OK;
+}

@@ -87,6 +87,8 @@ def _load(path: str | None = None):
         lib.oracle_fill.restype = ctypes.c_int64
         lib.oracle_peaks.argtypes = [gp, u32p, u32p, u32p, ctypes.c_int64]
         lib.oracle_peaks.restype = ctypes.c_int64
+        lib.oracle_readout.argtypes = [gp, u32p, ctypes.c_int64, P(ctypes.c_double)]
+        lib.oracle_readout.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -170,3 +172,19 @@ def peaks(g: OracleGrid, M: np.ndarray, capacity: int | None = None):
         raise ValueError("invalid grid")
     k = min(int(n), capacity)
     return cells[:k].copy(), votes[:k].copy(), int(n)
+
+
+def readout(g: OracleGrid, cells):
+    """Track parameters of peak cells: dict of t, p, a, b (int64) and A, B, rho, phi, theta."""
+    cells = np.ascontiguousarray(cells, dtype=np.uint32)
+    out = np.zeros((cells.size, 9), np.float64)
+    c = g._c()
+    rc = _load().oracle_readout(ctypes.byref(c), _ptr(cells, ctypes.c_uint32), cells.size,
+                                _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("invalid grid")
+    keys = ("t", "p", "a", "b", "A", "B", "rho", "phi", "theta")
+    d = {k: out[:, i] for i, k in enumerate(keys)}
+    for k in ("t", "p", "a", "b"):
+        d[k] = d[k].astype(np.int64)
+    return d

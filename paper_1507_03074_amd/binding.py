@@ -46,6 +46,18 @@ class Peak(ctypes.Structure):
     _fields_ = [("cell", ctypes.c_uint32), ("votes", ctypes.c_uint32)]
 
 
+class Track(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_uint32), ("votes", ctypes.c_uint32), ("t", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("A", ctypes.c_float), ("B", ctypes.c_float), ("rho", ctypes.c_float),
+                ("phi", ctypes.c_float), ("theta", ctypes.c_float)]
+
+
+TRACK_DTYPE = np.dtype([("cell", "<u4"), ("votes", "<u4"), ("t", "<i4"), ("p", "<i4"),
+                        ("a", "<i4"), ("b", "<i4"), ("A", "<f4"), ("B", "<f4"), ("rho", "<f4"),
+                        ("phi", "<f4"), ("theta", "<f4")])
+
+
 class Event(ctypes.Structure):
     _fields_ = [("hit_offset", ctypes.c_int64), ("n_hits", ctypes.c_int64),
                 ("peak_offset", ctypes.c_int64), ("peak_capacity", ctypes.c_int64)]
@@ -76,7 +88,7 @@ EXPORTS = ["ht_set_tuning", "ht_get_tuning", "ht_tables", "ht_fill", "ht_peaks",
            "ht_serve_create", "ht_serve_submit", "ht_serve_poll", "ht_serve_destroy",
            "ht_last_error", "ht_debug_hit_values", "ht_fill_atomic", "ht_tiling",
            "ht_profile_enable", "ht_profile_read", "ht_bench_hbm_write", "ht_bench_hbm_read",
-           "ht_bench_copy", "ht_bench_atomic_rand", "ht_bench_lds_atomic"]
+           "ht_bench_copy", "ht_bench_atomic_rand", "ht_bench_lds_atomic", "ht_readout"]
 
 _lib = None
 
@@ -106,6 +118,7 @@ def lib():
         "ht_fill_peaks_batch": ([gp, ctypes.POINTER(Event), i32, vp, vp, vp, vp, vp, vp, vp],
                                 ctypes.c_int),
         "ht_debug_hit_values": ([gp, vp, vp, vp, i64, vp, vp, vp, vp], ctypes.c_int),
+        "ht_readout": ([gp, vp, vp, i64, vp, vp], ctypes.c_int),
         "ht_serve_create": ([gp, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)], ctypes.c_int),
         "ht_serve_submit": ([vp, f32p, f32p, f32p, i64, ctypes.POINTER(ctypes.c_uint64)],
                             ctypes.c_int),
@@ -168,6 +181,15 @@ def _need_cuda(*ts):
             raise HTError(HT_EINVAL, "tensor arguments must be contiguous")
 
 
+def _need_out(*ts):
+    """Peak outputs: GPU tensors, or pinned host tensors (written directly by the kernels)."""
+    for t in ts:
+        if t is not None and not (t.is_cuda or t.is_pinned()):
+            raise HTError(HT_EINVAL, "output tensors must live on the GPU or in pinned host memory")
+        if t is not None and not t.is_contiguous():
+            raise HTError(HT_EINVAL, "tensor arguments must be contiguous")
+
+
 # ---------------------------------------------------------------------------------------------
 # Entry points (same names as the C ABI), tensors in, status out
 # ---------------------------------------------------------------------------------------------
@@ -220,14 +242,16 @@ def ht_fill(spec, x, y, z, acc, stream=None, atomic=False):
 
 def ht_peaks(spec, acc, out, capacity, n_found, stream=None):
     g = make_grid(spec)
-    _need_cuda(acc, out, n_found)
+    _need_cuda(acc)
+    _need_out(out, n_found)
     return check(lib().ht_peaks(ctypes.byref(g), _ptr(acc), _ptr(out), capacity, _ptr(n_found),
                                 _stream(stream)))
 
 
 def ht_fill_peaks(spec, x, y, z, acc, out, capacity, n_found, stream=None):
     g = make_grid(spec)
-    _need_cuda(x, y, z, acc, out, n_found)
+    _need_cuda(x, y, z, acc)
+    _need_out(out, n_found)
     return check(lib().ht_fill_peaks(ctypes.byref(g), _ptr(x), _ptr(y), _ptr(z), x.numel(),
                                      _ptr(acc), _ptr(out), capacity, _ptr(n_found),
                                      _stream(stream)))
@@ -235,11 +259,30 @@ def ht_fill_peaks(spec, x, y, z, acc, out, capacity, n_found, stream=None):
 
 def ht_fill_peaks_batch(spec, events, x, y, z, acc, out, n_found, stream=None):
     g = make_grid(spec)
-    _need_cuda(x, y, z, acc, out, n_found)
+    _need_cuda(x, y, z, acc)
+    _need_out(out, n_found)
     arr = (Event * len(events))(*events)
     return check(lib().ht_fill_peaks_batch(ctypes.byref(g), arr, len(events), _ptr(x), _ptr(y),
                                            _ptr(z), _ptr(acc), _ptr(out), _ptr(n_found),
                                            _stream(stream)))
+
+
+def ht_readout(spec, out, n_found, capacity, stream=None):
+    """Track parameters of a device peak list; returns a device uint8 tensor holding
+    ht_track[capacity] records (view with TRACK_DTYPE after copying to the host)."""
+    import torch
+    g = make_grid(spec)
+    _need_out(out, n_found)
+    tracks = torch.empty((max(capacity, 1) * TRACK_DTYPE.itemsize,), dtype=torch.uint8,
+                         device=out.device)
+    check(lib().ht_readout(ctypes.byref(g), _ptr(out), _ptr(n_found), capacity, _ptr(tracks),
+                           _stream(stream)))
+    return tracks
+
+
+def tracks_to_host(tracks, n_found, capacity):
+    k = min(int(n_found.item()), capacity)
+    return tracks.cpu().numpy().view(TRACK_DTYPE)[:k].copy()
 
 
 def ht_debug_hit_values(spec, x, y, z, stream=None):

@@ -266,15 +266,24 @@ DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
 // ---------------------------------------------------------------------------------------------
 static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 
-size_t event_scratch_bytes(const DevGrid& g, int64_t n)
+bool direct_lists(const DevGrid& g, int64_t n)
+{
+  return g.lds_fill && (size_t)g.n_slabs * (size_t)std::max<int64_t>(n, 1) * 16 <= kDirectListMax;
+}
+
+size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct)
 {
   const size_t nn = (size_t)std::max<int64_t>(n, 0);
   size_t b = 0;
   b += al(4 * ((size_t)g.n_slabs + 1));       // slab_off
-  b += al(16 * nn);                           // hit_slab
-  b += al(16 * nn);                           // hit_pos
-  b += al(16 * nn);                           // hit_rec
-  b += al(64 * nn);                           // list
+  if (direct) {
+    b += al(16 * (size_t)g.n_slabs * std::max<size_t>(nn, 1));  // list
+  } else {
+    b += al(16 * nn);                         // hit_slab
+    b += al(16 * nn);                         // hit_pos
+    b += al(16 * nn);                         // hit_rec
+    b += al(64 * nn);                         // list
+  }
   b += al(4 * (size_t)g.n_tiles);             // tile_cnt
   b += al(8 * (size_t)g.n_tiles * g.cand_cap);  // cand
   b += al(4 * (size_t)g.n_tiles);             // tile_pk
@@ -282,7 +291,7 @@ size_t event_scratch_bytes(const DevGrid& g, int64_t n)
   return b;
 }
 
-void carve_event_scratch(const DevGrid& g, int64_t n, char* p, EvDesc* ev)
+void carve_event_scratch(const DevGrid& g, int64_t n, bool direct, char* p, EvDesc* ev)
 {
   const size_t nn = (size_t)std::max<int64_t>(n, 0);
   auto take = [&p](size_t bytes) {
@@ -291,10 +300,19 @@ void carve_event_scratch(const DevGrid& g, int64_t n, char* p, EvDesc* ev)
     return r;
   };
   ev->slab_off = (uint32_t*)take(4 * ((size_t)g.n_slabs + 1));
-  ev->hit_slab = (int32_t*)take(16 * nn);
-  ev->hit_pos = (uint32_t*)take(16 * nn);
-  ev->hit_rec = (float4*)take(16 * nn);
-  ev->list = (float4*)take(64 * nn);
+  if (direct) {
+    ev->list_cap = (int64_t)std::max<size_t>(nn, 1);
+    ev->list = (float4*)take(16 * (size_t)g.n_slabs * (size_t)ev->list_cap);
+    ev->hit_slab = nullptr;
+    ev->hit_pos = nullptr;
+    ev->hit_rec = nullptr;
+  } else {
+    ev->list_cap = 0;
+    ev->hit_slab = (int32_t*)take(16 * nn);
+    ev->hit_pos = (uint32_t*)take(16 * nn);
+    ev->hit_rec = (float4*)take(16 * nn);
+    ev->list = (float4*)take(64 * nn);
+  }
   ev->tile_cnt = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->cand = (uint2*)take(8 * (size_t)g.n_tiles * g.cand_cap);
   ev->tile_pk = (uint32_t*)take(4 * (size_t)g.n_tiles);
@@ -306,8 +324,9 @@ void carve_event_scratch(const DevGrid& g, int64_t n, char* p, EvDesc* ev)
 struct Workspace {
   char* dev = nullptr;
   size_t bytes = 0;
-  uint32_t* ctr = nullptr;  // zeroed slab counters, kCounterBytes per event
+  uint32_t* ctr = nullptr;  // zeroed slab counter pairs, kCounterBytes per event slot
   int ctr_events = 0;
+  std::vector<uint8_t> parity;  // which array of each pair the next call counts into
   EvDesc* h_ev = nullptr;   // pinned staging of batch descriptors
   EvDesc* d_ev = nullptr;
   int ev_cap = 0;
@@ -358,10 +377,19 @@ int ensure_counters(Workspace* w, int n_ev, hipStream_t s)
     return fail_hip(e, "hipMalloc(counters)");
   if ((e = hipMemset(w->ctr, 0, kCounterBytes * want)) != hipSuccess) return fail_hip(e, "hipMemset(counters)");
   w->ctr_events = want;
+  w->parity.assign(want, 0);
   return HT_OK;
 }
 
-uint32_t* counters_of(Workspace* w, int i) { return w->ctr + (size_t)i * (kCounterBytes / 4); }
+// Counter arrays of event slot i for this call: count into the zero one, clear the other.
+void use_counters(Workspace* w, int i, EvDesc* d)
+{
+  uint32_t* pair = w->ctr + (size_t)i * (kCounterBytes / 4);
+  d->slab_cnt = pair + (w->parity[i] ? kMaxSlabs : 0);
+  d->slab_cnt_next = pair + (w->parity[i] ? 0 : kMaxSlabs);
+}
+
+void flip_counters(Workspace* w, int n) { for (int i = 0; i < n; ++i) w->parity[i] ^= 1; }
 
 int ensure_ev_staging(Workspace* w, int n_ev, hipStream_t s)
 {
@@ -471,14 +499,16 @@ int check_launch(hipError_t e, const char* what)
   return HT_OK;
 }
 
-int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, hipStream_t s)
+int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, bool direct,
+                 hipStream_t s)
 {
   EvDesc none;
   std::memset(&none, 0, sizeof(none));
   int rc;
   {
     StageTimer t("prep", s);
-    if ((rc = check_launch(launch_prep(g, none, d_ev, n_ev, max_hits, s), "prep launch"))) return rc;
+    if ((rc = check_launch(launch_prep(g, none, d_ev, n_ev, max_hits, direct && g.lds_fill, s), "prep launch")))
+      return rc;
   }
   if (g.lds_fill) {
     StageTimer t("fill", s);
@@ -496,6 +526,23 @@ int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hit
   return check_launch(launch_peaks(g, none, d_ev, n_ev, s), "peak launch");
 }
 
+// Outputs (peak list, count) may live in device memory or in pinned host memory that is
+// mapped into the device's address space; anything else would fault on the device, so it is
+// rejected here, on the host, before any launch.
+int check_accessible(const void* ptr, const char* what)
+{
+  if (!ptr) return HT_OK;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HT_EINVAL, "%s is neither device memory nor mapped pinned host memory", what);
+  }
+  if (attr.type == hipMemoryTypeHost && !attr.devicePointer)
+    return fail(HT_EINVAL, "%s is host memory without a device mapping", what);
+  return HT_OK;
+}
+
 int run_event(const ht_grid* grid, const float* x, const float* y, const float* z, int64_t n,
               uint32_t* acc, ht_peak* out, int64_t cap, int64_t* n_found, void* stream,
               bool do_fill, bool do_peaks, bool force_atomic)
@@ -509,14 +556,18 @@ int run_event(const ht_grid* grid, const float* x, const float* y, const float* 
   Prepared p;
   int rc = prepare(grid, stream, &p);
   if (rc) return rc;
+  if (do_peaks && ((rc = check_accessible(out, "out")) || (rc = check_accessible(n_found, "n_found"))))
+    return rc;
   const int64_t nh = do_fill ? n : 0;
+  const bool atomic = force_atomic || !p.g.lds_fill;
+  const bool direct = !atomic && direct_lists(p.g, nh);
   Workspace* w;
-  if ((rc = get_workspace(p.dev, p.s, event_scratch_bytes(p.g, nh), &w))) return rc;
+  if ((rc = get_workspace(p.dev, p.s, event_scratch_bytes(p.g, nh, direct), &w))) return rc;
   if ((rc = ensure_counters(w, 1, p.s))) return rc;
   EvDesc ev;
   std::memset(&ev, 0, sizeof(ev));
-  carve_event_scratch(p.g, nh, w->dev, &ev);
-  ev.slab_cnt = counters_of(w, 0);
+  carve_event_scratch(p.g, nh, direct, w->dev, &ev);
+  use_counters(w, 0, &ev);
   ev.x = x;
   ev.y = y;
   ev.z = z;
@@ -525,11 +576,12 @@ int run_event(const ht_grid* grid, const float* x, const float* y, const float* 
   ev.out = out;
   ev.cap = cap;
   ev.n_found = n_found;
-  const bool atomic = force_atomic || !p.g.lds_fill;
   if (do_fill) {
     {
       StageTimer t("prep", p.s);
-      if ((rc = check_launch(launch_prep(p.g, ev, nullptr, 1, nh, p.s), "prep launch"))) return rc;
+      rc = check_launch(launch_prep(p.g, ev, nullptr, 1, nh, direct, p.s), "prep launch");
+      flip_counters(w, 1);
+      if (rc) return rc;
     }
     if (atomic) {
       StageTimer t("fill_atomic", p.s);
@@ -630,11 +682,19 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
   }
   Prepared p;
   if ((rc = prepare(grid, stream, &p))) return rc;
+  if ((rc = check_accessible(out, "out")) || (rc = check_accessible(n_found, "n_found"))) return rc;
   std::vector<size_t> offs(n_events);
+  bool direct = p.g.lds_fill != 0;
+  size_t direct_bytes = 0;
+  for (int32_t i = 0; i < n_events; ++i) {
+    direct = direct && direct_lists(p.g, events[i].n_hits);
+    direct_bytes += event_scratch_bytes(p.g, events[i].n_hits, true);
+  }
+  if (direct_bytes > ((size_t)8 << 30)) direct = false;
   for (int32_t i = 0; i < n_events; ++i) {
     max_hits = std::max(max_hits, events[i].n_hits);
     offs[i] = (size_t)total_scratch;
-    total_scratch += (int64_t)event_scratch_bytes(p.g, events[i].n_hits);
+    total_scratch += (int64_t)event_scratch_bytes(p.g, events[i].n_hits, direct);
   }
   Workspace* w;
   if ((rc = get_workspace(p.dev, p.s, (size_t)total_scratch, &w))) return rc;
@@ -645,8 +705,8 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
     const ht_event& ev = events[i];
     EvDesc& d = w->h_ev[i];
     std::memset(&d, 0, sizeof(d));
-    carve_event_scratch(p.g, ev.n_hits, w->dev + offs[i], &d);
-    d.slab_cnt = counters_of(w, i);
+    carve_event_scratch(p.g, ev.n_hits, direct, w->dev + offs[i], &d);
+    use_counters(w, i, &d);
     d.x = x ? x + ev.hit_offset : nullptr;
     d.y = y ? y + ev.hit_offset : nullptr;
     d.z = z ? z + ev.hit_offset : nullptr;
@@ -662,19 +722,20 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
   while (blocks * 256 < max_hits) blocks *= 2;
   const int64_t max_hits_b = max_hits > 0 ? blocks * 256 : 0;
   hipError_t e;
+  flip_counters(w, n_events);  // the descriptors above hold this call's counter arrays
   if (env_int("HT_BATCH_GRAPH", 1) == 0) {
     e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, p.s);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(descriptors)");
     if ((e = hipEventRecord(w->ev_copied, p.s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
-    return launch_batch(p.g, w->d_ev, n_events, max_hits_b, p.s);
+    return launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, p.s);
   }
   // graph key: everything the captured launches depend on besides the descriptor contents
-  std::vector<unsigned char> key(sizeof(DevGrid) + 3 * sizeof(int64_t) + 2 * sizeof(void*));
+  std::vector<unsigned char> key(sizeof(DevGrid) + 4 * sizeof(int64_t) + 2 * sizeof(void*));
   {
     unsigned char* q = key.data();
     std::memcpy(q, &p.g, sizeof(DevGrid));
     q += sizeof(DevGrid);
-    const int64_t ints[3] = {n_events, max_hits_b, p.dev};
+    const int64_t ints[4] = {n_events, max_hits_b, p.dev, direct ? 1 : 0};
     std::memcpy(q, ints, sizeof(ints));
     q += sizeof(ints);
     const void* ptrs[2] = {w->d_ev, w->h_ev};
@@ -692,7 +753,8 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
       return fail_hip(e, "hipStreamBeginCapture");
     t_capturing = true;
     e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, w->capture);
-    int lrc = e == hipSuccess ? launch_batch(p.g, w->d_ev, n_events, max_hits_b, w->capture) : HT_EDEVICE;
+    int lrc = e == hipSuccess ? launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, w->capture)
+                              : HT_EDEVICE;
     t_capturing = false;
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(w->capture, &graph);
@@ -744,6 +806,22 @@ int ht_get_tuning(const ht_grid* grid, ht_tuning* tuning)
   tuning->cand_cap = t.cand_cap;
   tuning->nt_store = t.nt_store;
   return HT_OK;
+}
+
+int ht_readout(const ht_grid* grid, const ht_peak* peaks, const int64_t* n_found, int64_t capacity,
+               ht_track* tracks, void* stream)
+{
+  if (capacity < 0 || capacity > ((int64_t)1 << 31)) return fail(HT_EINVAL, "capacity out of range");
+  if (!n_found || (capacity > 0 && (!peaks || !tracks))) return fail(HT_EINVAL, "NULL readout argument");
+  Prepared p;
+  int rc = prepare(grid, stream, &p);
+  if (rc) return rc;
+  if ((rc = check_accessible(peaks, "peaks")) || (rc = check_accessible(n_found, "n_found")) ||
+      (rc = check_accessible(tracks, "tracks")))
+    return rc;
+  const double db = ((double)grid->b_max - (double)grid->b_min) / (double)grid->n_b;
+  return check_launch(launch_readout(p.g, peaks, n_found, capacity, tracks, (double)grid->b_min, db, p.s),
+                      "readout launch");
 }
 
 int ht_debug_hit_values(const ht_grid* grid, const float* x, const float* y, const float* z,

@@ -13,9 +13,13 @@ namespace ht {
 
 // Largest number of (theta, phi) cells (slabs); their counters live in LDS during the prep.
 constexpr int kMaxSlabs = 4096;
-// Bytes of the per-event slab counters. They must be zero before a fill and the fill leaves
-// them zero, so they live in memory of their own that is cleared once when allocated.
-constexpr size_t kCounterBytes = sizeof(uint32_t) * kMaxSlabs;
+// Per-event slab counters: a pair of arrays used alternately by successive calls. A call counts
+// into the array that is zero and clears the other one for the next call, so no call needs a
+// separate clearing launch. They live in memory of their own, cleared once when allocated.
+constexpr size_t kCounterBytes = 2 * sizeof(uint32_t) * kMaxSlabs;
+// Direct slab lists (one fixed-capacity list per slab, capacity = the event's hit count) are
+// used while they need at most this many bytes per event; above it, a counting sort.
+constexpr size_t kDirectListMax = (size_t)1 << 29;
 
 // Grid constants and tables as the kernels see them (passed by value as a kernel argument).
 struct DevGrid {
@@ -48,26 +52,30 @@ struct EvDesc {
   int64_t cap;
   int64_t* n_found;     // [1]
   // scratch
-  uint32_t* slab_cnt;   // [n_slabs] counters (dedicated memory, see kCounterBytes)
-  uint32_t* slab_off;   // [n_slabs + 1]
+  uint32_t* slab_cnt;       // [n_slabs] counters of this call, zero on entry (kCounterBytes)
+  uint32_t* slab_cnt_next;  // [n_slabs] the other counter array, cleared by this call
+  int64_t list_cap;         // > 0: direct lists, list_cap records per slab; 0: counting sort
+  uint32_t* slab_off;       // [n_slabs + 1] (counting sort)
   int32_t* hit_slab;    // [4 n_hits] slab of each (hit, cell) or -1
   uint32_t* hit_pos;    // [4 n_hits] position of the (hit, cell) in its slab list
   float4* hit_rec;      // [n_hits] (x, r2, k, 0)
-  float4* list;         // [4 n_hits] hit records bucketed by slab
+  float4* list;         // hit records bucketed by slab: [n_slabs * list_cap] or [4 n_hits]
   uint32_t* tile_cnt;   // [n_tiles] candidates (cells >= threshold) per tile
   uint2* cand;          // [n_tiles * cand_cap] (cell, votes) of the candidates, ascending per tile
   uint32_t* tile_pk;    // [n_tiles] peaks per tile
   uint32_t* group_pk;   // [n_groups] peaks per group of tiles
 };
 
+// Whether an event of n_hits hits uses direct slab lists (see kDirectListMax).
+bool direct_lists(const DevGrid& g, int64_t n_hits);
 // Bytes of per-event scratch for a grid tiling and an event size, and the carving of it.
-size_t event_scratch_bytes(const DevGrid& g, int64_t n_hits);
-void carve_event_scratch(const DevGrid& g, int64_t n_hits, char* base, EvDesc* ev);
+size_t event_scratch_bytes(const DevGrid& g, int64_t n_hits, bool direct);
+void carve_event_scratch(const DevGrid& g, int64_t n_hits, bool direct, char* base, EvDesc* ev);
 
 // Kernel launchers (ht_kernels.hip). `evs` is a device array of n_ev descriptors, or nullptr
 // for a single event passed by value in `ev0`. `max_hits` bounds n_hits over the events.
 hipError_t launch_prep(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
-                       int64_t max_hits, hipStream_t s);
+                       int64_t max_hits, bool direct, hipStream_t s);
 hipError_t launch_fill(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                        bool emit_candidates, hipStream_t s);
 hipError_t launch_candidates(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
@@ -78,6 +86,9 @@ hipError_t launch_peaks(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, 
 // fallback for B rows too wide for an LDS tile).
 hipError_t launch_fill_atomic(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                               int64_t max_hits, hipStream_t s);
+
+hipError_t launch_readout(const DevGrid& g, const ht_peak* peaks, const int64_t* n_found, int64_t cap,
+                          ht_track* tracks, double b_min, double db, hipStream_t s);
 
 size_t fill_lds_bytes(const DevGrid& g);
 int n_groups(const DevGrid& g);
@@ -91,6 +102,7 @@ uint64_t n_cells(const ht_grid& g);
 int make_device_grid(const ht_grid& g, int dev, DevGrid* out);
 // The whole batched pipeline (prep, fill with candidates, peaks) for n_ev events whose
 // descriptors are already in device memory.
-int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, hipStream_t s);
+int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, bool direct,
+                 hipStream_t s);
 
 }  // namespace ht

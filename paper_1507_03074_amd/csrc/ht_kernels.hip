@@ -3,11 +3,11 @@
 // Pipeline (paper section 2: every hit votes along its circles through the interaction point,
 // then the local maxima above a threshold are the track candidates). Every kernel takes a batch
 // of events (grid.y = event), so one launch per stage serves a single event or a whole batch:
-//   k_prep        per hit: validity, r2, k = 1/(2y), theta/phi half-sectors and the 2-4
-//                 (theta, phi) cells; the (hit, cell) records are counted per slab (one slab =
-//                 the A x B plane of one (theta, phi) cell) with LDS-aggregated atomics
-//   k_bucket      every workgroup scans the slab counts in LDS and scatters its hits' records
-//                 into per-slab lists (a counting sort)
+//   k_prep_direct per hit: validity, r2, k = 1/(2y), theta/phi half-sectors and the 2-4
+//                 (theta, phi) cells; the (hit, cell) records go to fixed-capacity per-slab lists
+//                 (one slab = the A x B plane of one (theta, phi) cell), their positions reserved
+//                 with LDS-aggregated atomics. Very large events use a counting sort instead:
+//                 k_prep counts, then k_bucket scans the counts in LDS and scatters.
 //   k_fill        one workgroup per (slab, tile of A rows): the slab's records vote into an LDS
 //                 tile (ds_add), then every cell of the tile is written to HBM once with
 //                 coalesced 16-byte stores (so the matrix needs no memset), and the cells >= threshold
@@ -154,12 +154,52 @@ __device__ HitPrep prep_hit(const DevGrid& g, float x, float y, float z)
   return h;
 }
 
-// Counts per slab: in LDS per workgroup, then one global atomic per (workgroup, slab) reserves
-// the workgroup's range of each slab list. slab_cnt starts at zero (the fill clears it again).
+// Direct lists: counts per slab in LDS per workgroup, one global atomic per (workgroup, slab)
+// reserves the workgroup's range of each slab's fixed-capacity list, then the records are
+// written there. slab_cnt is zero on entry and ends holding the list lengths; workgroup 0 clears
+// the other counter array for the next call.
+__global__ __launch_bounds__(kBlock) void k_prep_direct(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  __shared__ uint32_t lcnt[kMaxSlabs];
+  EvDesc e = load_ev(ev0, evs);
+  // clear all of the other array: an earlier call on a grid with more slabs may have used
+  // entries past this grid's n_slabs
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < kMaxSlabs; i += kBlock) e.slab_cnt_next[i] = 0u;
+  if ((int64_t)blockIdx.x * kBlock >= e.n_hits) return;  // uniform: whole block idle
+  for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) lcnt[i] = 0u;
+  __syncthreads();
+  const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  HitPrep p;
+  p.n = 0;
+  uint32_t local[4] = {0u, 0u, 0u, 0u};
+  if (h < e.n_hits) {
+    p = prep_hit(g, e.x[h], e.y[h], e.z[h]);
+    for (int q = 0; q < p.n; ++q) local[q] = atomicAdd(&lcnt[p.slab[q]], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) {
+    uint32_t c = lcnt[i];
+    if (c) lcnt[i] = atomicAdd(&e.slab_cnt[i], c);
+  }
+  __syncthreads();
+  if (h < e.n_hits) {
+    const float4 rec = make_float4(p.x, p.r2, p.k, 0.0f);
+    for (int q = 0; q < p.n; ++q)
+      e.list[(size_t)p.slab[q] * (size_t)e.list_cap + lcnt[p.slab[q]] + local[q]] = rec;
+  }
+}
+
+// Counting sort, first pass: counts per slab (LDS, then one global atomic per workgroup and
+// slab) and each record's position within its slab. Workgroup 0 clears the other counter array.
 __global__ __launch_bounds__(kBlock) void k_prep(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   __shared__ uint32_t lcnt[kMaxSlabs];
   EvDesc e = load_ev(ev0, evs);
+  // clear all of the other array: an earlier call on a grid with more slabs may have used
+  // entries past this grid's n_slabs
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < kMaxSlabs; i += kBlock) e.slab_cnt_next[i] = 0u;
   if ((int64_t)blockIdx.x * kBlock >= e.n_hits) return;  // uniform: whole block idle
   for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) lcnt[i] = 0u;
   __syncthreads();
@@ -294,18 +334,21 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
   const u32x4 zero4 = {0u, 0u, 0u, 0u};
   for (uint32_t i = threadIdx.x; i < Lpad / 4; i += kBlock) s4[i] = zero4;
   if (EMIT && threadIdx.x == 0) *s_ncand = 0u;
-  // the slab counts of this event are consumed (k_bucket): leave them zero for the next use
-  if (tile == 0)
-    for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) e.slab_cnt[i] = 0u;
   __syncthreads();
 
-  const uint32_t beg = e.slab_off[slab];
-  const uint32_t end = e.slab_off[slab + 1];
+  size_t beg, end;
+  if (e.list_cap > 0) {
+    beg = (size_t)slab * (size_t)e.list_cap;
+    end = beg + e.slab_cnt[slab];
+  } else {
+    beg = e.slab_off[slab];
+    end = e.slab_off[slab + 1];
+  }
   float a2r[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) a2r[r] = g.a2[min(a0 + r, g.n_a - 1)];
   const float b_min = g.b_min, inv_db = g.inv_db, nb_f = g.nb_f;
-  for (uint32_t h = beg + threadIdx.x; h < end; h += kBlock) {
+  for (size_t h = beg + threadIdx.x; h < end; h += kBlock) {
     const float4 rec = e.list[h];
     const float x = rec.x, r2 = rec.y, k = rec.z;
 #pragma unroll
@@ -663,8 +706,6 @@ __global__ __launch_bounds__(kBlock) void k_zero_acc(DevGrid g, EvDesc ev0, cons
 __global__ __launch_bounds__(kBlock) void k_fill_atomic(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   EvDesc e = load_ev(ev0, evs);
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) e.slab_cnt[i] = 0u;
   const int64_t h = blockIdx.x;
   if (h >= e.n_hits) return;
   int slabs[4];
@@ -688,6 +729,36 @@ __global__ __launch_bounds__(kBlock) void k_fill_atomic(DevGrid g, EvDesc ev0, c
         atomicAdd(&e.acc[((uint64_t)slabs[q] * g.n_a + i) * g.n_b + j], 1u);
     }
   }
+}
+
+// Track parameters of each peak: bin indices, bin-centre (A, B), rho, phi, theta in double.
+__global__ __launch_bounds__(kBlock) void k_readout(DevGrid g, const ht_peak* peaks, const int64_t* n_found,
+                                                    int64_t cap, ht_track* tracks, double b_min,
+                                                    double db)
+{
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t n = min(*n_found, cap);
+  if (i >= n) return;
+  const ht_peak pk = peaks[i];
+  uint32_t t, p, a, b;
+  cell_coords(g, pk.cell, &t, &p, &a, &b);
+  const double A = 0.5 * (double)g.a2[a];
+  const double B = b_min + ((double)b + 0.5) * db;
+  double phi = atan2(B, A);
+  if (phi < 0.0) phi += 2.0 * 3.14159265358979323846;
+  ht_track tr;
+  tr.cell = pk.cell;
+  tr.votes = pk.votes;
+  tr.t = (int32_t)t;
+  tr.p = (int32_t)p;
+  tr.a = (int32_t)a;
+  tr.b = (int32_t)b;
+  tr.A = (float)A;
+  tr.B = (float)B;
+  tr.rho = (float)sqrt(A * A + B * B);
+  tr.phi = (float)phi;
+  tr.theta = (float)(((double)t + 0.5) * 3.14159265358979323846 / (double)g.n_theta);
+  tracks[i] = tr;
 }
 
 __global__ __launch_bounds__(kBlock) void k_debug_hits(DevGrid g, const float* x, const float* y,
@@ -749,10 +820,14 @@ size_t fill_lds_bytes(const DevGrid& g)
 }
 
 hipError_t launch_prep(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
-                       int64_t max_hits, hipStream_t s)
+                       int64_t max_hits, bool direct, hipStream_t s)
 {
   const unsigned blocks = (unsigned)std::max<int64_t>(1, (max_hits + kBlock - 1) / kBlock);
-  if (max_hits > 0) hipLaunchKernelGGL(k_prep, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
+  if (direct) {
+    hipLaunchKernelGGL(k_prep_direct, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_prep, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
   hipLaunchKernelGGL(k_bucket, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
   return hipGetLastError();
 }
@@ -792,6 +867,15 @@ hipError_t launch_fill_atomic(const DevGrid& g, const EvDesc& ev0, const EvDesc*
   hipLaunchKernelGGL(k_zero_acc, dim3(4096, n_ev), dim3(kBlock), 0, s, g, ev0, evs, cells);
   hipLaunchKernelGGL(k_fill_atomic, dim3((unsigned)std::max<int64_t>(max_hits, 1), n_ev), dim3(kBlock), 0,
                      s, g, ev0, evs);
+  return hipGetLastError();
+}
+
+hipError_t launch_readout(const DevGrid& g, const ht_peak* peaks, const int64_t* n_found, int64_t cap,
+                          ht_track* tracks, double b_min, double db, hipStream_t s)
+{
+  if (cap > 0)
+    hipLaunchKernelGGL(k_readout, dim3((unsigned)((cap + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g,
+                       peaks, n_found, cap, tracks, b_min, db);
   return hipGetLastError();
 }
 

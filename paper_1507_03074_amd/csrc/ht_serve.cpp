@@ -5,8 +5,9 @@
 // vote matrix, scratch, hits and peak list), and the number of slots is what the HBM budget
 // holds -- groups whatever is admitted (up to max_batch) into one batched launch, and puts
 // successive batches on different streams so that they overlap on the GPU. When a batch's
-// completion event fires, its peak lists are handed to the requests and the slots go back to
-// the pool, so later arrivals are admitted while earlier batches are still running.
+// completion event fires, its peak lists (written by the peak kernel straight into mapped,
+// coherent pinned host memory) are handed to the requests and the slots go back to the pool,
+// so later arrivals are admitted while earlier batches are still running.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -43,14 +44,15 @@ struct Request {
 };
 
 struct Slot {
-  uint32_t* ctr;      // zeroed slab counters (the fill leaves them zero)
+  uint32_t* ctr;      // slab counter pair (see kCounterBytes)
+  int parity;         // which array of the pair the next batch counts into
   uint32_t* acc;
   char* scratch;
   float* hits;
-  ht_peak* d_out;
+  ht_peak* h_out;     // pinned host peak list, written by the kernels through d_out
+  int64_t* h_nfound;  // pinned host count, written through d_nfound
+  ht_peak* d_out;     // device addresses of h_out / h_nfound
   int64_t* d_nfound;
-  ht_peak* h_out;     // pinned
-  int64_t* h_nfound;  // pinned
 };
 
 struct Batch {
@@ -70,6 +72,7 @@ struct ht_server {
   int dev = 0;
   uint64_t cells = 0;
   size_t scratch_bytes = 0;
+  bool direct = false;
   char* arena = nullptr;        // device: all slots
   uint32_t* ctr = nullptr;      // device: slab counters of all slots
   char* host_out = nullptr;     // pinned: per-slot peak lists and counts
@@ -130,14 +133,16 @@ int launch(ht_server* sv, Batch& b)
       return fail_hip(e, "hipMemcpyAsync(hits)");
     EvDesc& d = sv->h_ev[b.stream][i];
     std::memset(&d, 0, sizeof(d));
-    carve_event_scratch(sv->g, mh, sl.scratch, &d);
-    d.slab_cnt = sl.ctr;
+    carve_event_scratch(sv->g, mh, sv->direct, sl.scratch, &d);
+    d.slab_cnt = sl.ctr + (sl.parity ? kMaxSlabs : 0);
+    d.slab_cnt_next = sl.ctr + (sl.parity ? 0 : kMaxSlabs);
+    sl.parity ^= 1;
     d.x = sl.hits;
     d.y = sl.hits + r->n;
     d.z = sl.hits + 2 * r->n;
     d.n_hits = r->n;
     d.acc = sl.acc;
-    d.out = sl.d_out;
+    d.out = sl.d_out;  // mapped pinned host memory: the kernels write the peaks to the host
     d.cap = sv->opts.peak_capacity;
     d.n_found = sl.d_nfound;
     max_n = std::max(max_n, r->n);
@@ -145,15 +150,8 @@ int launch(ht_server* sv, Batch& b)
   if ((e = hipMemcpyAsync(sv->d_ev[b.stream], sv->h_ev[b.stream], sizeof(EvDesc) * b.reqs.size(),
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail_hip(e, "hipMemcpyAsync(descriptors)");
-  int rc = launch_batch(sv->g, sv->d_ev[b.stream], (int)b.reqs.size(), max_n, s);
+  int rc = launch_batch(sv->g, sv->d_ev[b.stream], (int)b.reqs.size(), max_n, sv->direct, s);
   if (rc) return rc;
-  for (Request* r : b.reqs) {
-    Slot& sl = sv->slots[r->slot];
-    if ((e = hipMemcpyAsync(sl.h_nfound, sl.d_nfound, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(ht_peak) * (size_t)sv->opts.peak_capacity,
-                            hipMemcpyDeviceToHost, s)) != hipSuccess)
-      return fail_hip(e, "hipMemcpyAsync(peaks)");
-  }
   if ((e = hipEventRecord(sv->done_ev[b.stream], s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
   return HT_OK;
 }
@@ -255,9 +253,9 @@ int ht_serve_create(const ht_grid* grid, const ht_serve_opts* opts, ht_server** 
     return rc;
   }
   sv->cells = n_cells(*grid);
-  sv->scratch_bytes = event_scratch_bytes(sv->g, opts->max_hits);
-  const size_t slot_bytes = al(4 * sv->cells) + al(sv->scratch_bytes) + al(12 * (size_t)opts->max_hits) +
-                            al(sizeof(ht_peak) * (size_t)opts->peak_capacity) + al(8);
+  sv->direct = direct_lists(sv->g, opts->max_hits);
+  sv->scratch_bytes = event_scratch_bytes(sv->g, opts->max_hits, sv->direct);
+  const size_t slot_bytes = al(4 * sv->cells) + al(sv->scratch_bytes) + al(12 * (size_t)opts->max_hits);
   const int64_t n_slots = std::min<int64_t>(opts->hbm_budget_bytes / (int64_t)slot_bytes, 4096);
   if (n_slots < 1) {
     delete sv;
@@ -274,8 +272,8 @@ int ht_serve_create(const ht_grid* grid, const ht_serve_opts* opts, ht_server** 
   if ((e = hipMemset(sv->ctr, 0, kCounterBytes * (size_t)n_slots)) != hipSuccess)
     return bail(fail_hip(e, "hipMemset(server counters)"));
   const size_t host_slot = al(sizeof(ht_peak) * (size_t)opts->peak_capacity) + al(8);
-  if ((e = hipHostMalloc((void**)&sv->host_out, host_slot * (size_t)n_slots, hipHostMallocDefault)) !=
-      hipSuccess)
+  if ((e = hipHostMalloc((void**)&sv->host_out, host_slot * (size_t)n_slots,
+                         hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
     return bail(fail_hip(e, "hipHostMalloc(server results)"));
   if ((e = hipHostMalloc((void**)&sv->stage_pool, 12 * (size_t)opts->max_hits * opts->queue_depth,
                          hipHostMallocDefault)) != hipSuccess)
@@ -284,18 +282,22 @@ int ht_serve_create(const ht_grid* grid, const ht_serve_opts* opts, ht_server** 
     char* p = sv->arena + (size_t)i * slot_bytes;
     Slot s;
     s.ctr = sv->ctr + (size_t)i * (kCounterBytes / 4);
+    s.parity = 0;
     s.acc = (uint32_t*)p;
     p += al(4 * sv->cells);
     s.scratch = p;
     p += al(sv->scratch_bytes);
     s.hits = (float*)p;
-    p += al(12 * (size_t)opts->max_hits);
-    s.d_out = (ht_peak*)p;
-    p += al(sizeof(ht_peak) * (size_t)opts->peak_capacity);
-    s.d_nfound = (int64_t*)p;
     char* h = sv->host_out + (size_t)i * host_slot;
     s.h_out = (ht_peak*)h;
     s.h_nfound = (int64_t*)(h + al(sizeof(ht_peak) * (size_t)opts->peak_capacity));
+    void* dp = nullptr;
+    if ((e = hipHostGetDevicePointer(&dp, s.h_out, 0)) != hipSuccess || !dp)
+      return bail(fail_hip(e, "hipHostGetDevicePointer(results)"));
+    s.d_out = (ht_peak*)dp;
+    if ((e = hipHostGetDevicePointer(&dp, s.h_nfound, 0)) != hipSuccess || !dp)
+      return bail(fail_hip(e, "hipHostGetDevicePointer(results)"));
+    s.d_nfound = (int64_t*)dp;
     sv->slots.push_back(s);
     sv->free_slots.push_back((int)(n_slots - 1 - i));
   }

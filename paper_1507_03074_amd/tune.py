@@ -71,6 +71,7 @@ def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool 
             B.ht_set_tuning(spec, cand)
         except B.HTError:
             continue
+        cand = B.ht_get_tuning(spec)  # the effective shape, defaults filled in
         exact = True
         for (x, y, z), (racc, rpk) in zip(hits, ref):
             B.ht_fill_peaks(spec, x, y, z, acc, out, capacity, nf)

@@ -466,3 +466,99 @@ def test_autotuner_keeps_results_and_caches(gpu, tmp_path):
         assert_same(CFG0, gM, gc, gv, gn, M, oc, ov, on)
     finally:
         B.ht_set_tuning(CFG0)
+
+
+def test_readout_matches_oracle(gpu):
+    """ht_readout (device, double rounded to float) against the oracle's readout in double:
+    indices and votes exact, A and B exact (bin centres), rho/phi/theta within 1 ulp of float."""
+    import torch
+    from oracle import oracle
+    B = gpu
+    for spec, wl, e in ((CFG0, 0, 1), (CFG1, 1, 2), (synth.GridSpec(3, 5, 7, 9, threshold=2), 0, 3)):
+        say("readout", spec.shape)
+        ev = synth.make_event(wl, e)
+        xd, yd, zd = B.hits_to_device(ev.x, ev.y, ev.z)
+        cap = 1 << 15
+        acc = B.new_acc(spec)
+        out, nf = B.new_peaks(cap)
+        B.ht_fill_peaks(spec, xd, yd, zd, acc, out, cap, nf)
+        tr = B.tracks_to_host(B.ht_readout(spec, out, nf, cap), nf, cap)
+        torch.cuda.synchronize()
+        cells, votes, n = B.peaks_to_host(out, nf, cap)
+        assert n > 0 and len(tr) == n
+        r = oracle.readout(oracle.OracleGrid(*spec.as_tuple()), cells)
+        assert np.array_equal(tr["cell"], cells) and np.array_equal(tr["votes"], votes)
+        for k in ("t", "p", "a", "b"):
+            assert np.array_equal(tr[k], r[k]), k
+        for k in ("A", "B", "rho", "phi", "theta"):
+            ref = r[k].astype(np.float32)
+            diff = np.abs(tr[k].astype(np.float64) - ref.astype(np.float64))
+            assert np.all(diff <= np.spacing(np.abs(ref)).astype(np.float64)), k
+
+
+def test_physics_single_track_found(gpu):
+    """A noiseless single track: the peak's readout gives the generating (A, B) bin centre."""
+    import torch
+    from paper_1507_03074_amd import physics
+    B = gpu
+    spec = synth.GridSpec(4, 16, 1024, 1024, threshold=12)
+    A0 = -2000.0 + (700 + 0.5) * 4000.0 / 1024
+    B0 = -2000.0 + (300 + 0.5) * 4000.0 / 1024
+    x, y, z, _, _ = synth.helix_hits([A0], [B0], [1.0], [0.3])
+    x, y, z = (v.astype(np.float32) for v in (x, y, z))
+    xd, yd, zd = B.hits_to_device(x, y, z)
+    acc = B.new_acc(spec)
+    out, nf = B.new_peaks(64)
+    B.ht_fill_peaks(spec, xd, yd, zd, acc, out, 64, nf)
+    tr = B.tracks_to_host(B.ht_readout(spec, out, nf, 64), nf, 64)
+    torch.cuda.synchronize()
+    assert len(tr) == 1 and tr["votes"][0] == 12
+    assert (tr["a"][0], tr["b"][0]) == (700, 300)
+    assert tr["A"][0] == np.float32(A0) and tr["B"][0] == np.float32(B0)
+    fa, fb = physics.lsq_circle_through_origin(x, y)
+    assert abs(fa - A0) < 1e-2 and abs(fb - B0) < 1e-2
+
+
+def test_peaks_written_to_pinned_host_memory(gpu):
+    """The peak kernels write straight into pinned host memory (no copy); results equal the
+    oracle's on consecutive events, so no stale data survives between calls."""
+    import torch
+    B = gpu
+    cap = 4096
+    h_out = torch.zeros((cap, 2), dtype=torch.int32, pin_memory=True)
+    h_nf = torch.zeros(1, dtype=torch.int64, pin_memory=True)
+    acc = B.new_acc(CFG0)
+    for e in range(8):
+        ev = synth.make_event(0, 700 + e)
+        say("pinned output, event", 700 + e)
+        xd, yd, zd = B.hits_to_device(ev.x, ev.y, ev.z)
+        B.ht_fill_peaks(CFG0, xd, yd, zd, acc, h_out, cap, h_nf)
+        torch.cuda.synchronize()
+        M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
+        assert int(h_nf[0]) == on
+        got = h_out.numpy().view(np.uint32)[:on]
+        assert np.array_equal(got[:, 0], oc) and np.array_equal(got[:, 1], ov)
+    # ordinary (unpinned) host memory is refused on the host, before any launch
+    plain = torch.zeros((cap, 2), dtype=torch.int32)
+    g = B.make_grid(CFG0)
+    rc = B.lib().ht_fill_peaks(ctypes.byref(g), ctypes.c_void_p(xd.data_ptr()),
+                               ctypes.c_void_p(yd.data_ptr()), ctypes.c_void_p(zd.data_ptr()),
+                               xd.numel(), ctypes.c_void_p(acc.data_ptr()),
+                               ctypes.c_void_p(plain.data_ptr()), cap,
+                               ctypes.c_void_p(h_nf.data_ptr()), None)
+    assert rc == B.HT_EINVAL
+
+
+def test_alternating_grid_sizes_keep_counters_clean(gpu):
+    """Calls alternate between grids with many and few (theta, phi) cells on one stream; the
+    per-slab counters carried between calls must not leak counts from one grid to the next."""
+    B = gpu
+    big = synth.GridSpec(4, 16, 130, 66, threshold=4)
+    small = synth.GridSpec(3, 5, 7, 9, threshold=2)
+    wide = synth.GridSpec(8, 32, 16, 16, threshold=3)
+    for k, spec in enumerate([big, small, big, wide, small, big, wide, big]):
+        say("alternating grids, call", k, spec.shape)
+        x, y, z = random_hits(100 + k, 300)
+        gM, gc, gv, gn = gpu_fused(B, spec, x, y, z)
+        M, votes, oc, ov, on = oracle_run(spec, x, y, z)
+        assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "call %d" % k)

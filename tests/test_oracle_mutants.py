@@ -49,6 +49,8 @@ MUTANTS = [
     ("theta boundary loop off by one", "for (int32_t m = 1; m < 2 * g->n_theta; ++m)\n    s_th",
      "for (int32_t m = 1; m < 2 * g->n_theta - 1; ++m)\n    s_th"),
     ("r2 with a minus", "float r2 = xx + yy;", "float r2 = xx - yy;"),
+    ("readout phi not wrapped", "if (phi < 0.0) phi += 2.0 * kPi;", "(void)0;"),
+    ("readout B at the bin edge", "((double)b + 0.5) * db", "((double)b) * db"),
 ]
 
 

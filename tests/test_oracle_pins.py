@@ -471,3 +471,25 @@ def test_regression_fixtures(oracle_mod):
         cells, vv, n = oracle_mod.peaks(g, M)
         assert votes == rec["votes"]
         assert [[int(c), int(v)] for c, v in zip(cells, vv)] == rec["peaks"]
+
+
+@pytest.mark.pin
+@pytest.mark.parametrize("spec", [CFG0, RAGGED, CFG4])
+def test_readout_matches_definition(oracle_mod, spec):
+    """rho = sqrt(A^2 + B^2) and phi = atan2(B, A) in [0, 2 pi) of the bin centres (section 2)."""
+    rng = np.random.default_rng(4)
+    cells = rng.integers(0, spec.n_cells, 500).astype(np.uint32)
+    r = oracle_mod.readout(og(oracle_mod, spec), cells)
+    t, p, a, b = np.unravel_index(cells.astype(np.int64), spec.shape)
+    assert np.array_equal(r["t"], t) and np.array_equal(r["p"], p)
+    assert np.array_equal(r["a"], a) and np.array_equal(r["b"], b)
+    for i in range(0, 500, 7):
+        A = em.F(spec.a_min) + (a[i] + Fraction(1, 2)) * (em.F(spec.a_max) - em.F(spec.a_min)) / spec.n_a
+        Bc = em.F(spec.b_min) + (b[i] + Fraction(1, 2)) * (em.F(spec.b_max) - em.F(spec.b_min)) / spec.n_b
+        assert abs(r["A"][i] - float(A)) <= 1e-9 * max(1.0, abs(float(A)))
+        assert abs(r["B"][i] - float(Bc)) <= 1e-9 * max(1.0, abs(float(Bc)))
+        assert r["rho"][i] == pytest.approx(math.hypot(float(A), float(Bc)), rel=1e-12)
+        phi = math.atan2(float(Bc), float(A)) % (2 * math.pi)
+        assert r["phi"][i] == pytest.approx(phi, abs=1e-12)
+        assert 0.0 <= r["phi"][i] < 2 * math.pi
+        assert r["theta"][i] == pytest.approx((t[i] + 0.5) * math.pi / spec.n_theta, rel=1e-14)
