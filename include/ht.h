@@ -91,7 +91,10 @@ typedef struct ht_tuning {
   int32_t rows;         /* A rows per fill tile: a power of two <= 64 whose rows x n_b uint32
                            counters fit in 56 KiB of LDS */
   int32_t group_tiles;  /* tiles per workgroup of the peak search: 16, 32 or 64 */
-  int32_t cand_cap;     /* candidate slots per tile: a power of two in [2, 4096] */
+  int32_t cand_cap;     /* candidate-pool entries per tile, a power of two <= 4096: the cells
+                           at or above the threshold of all tiles share a pool of
+                           n_tiles * cand_cap entries; tiles that do not fit are searched
+                           densely (slower, same results) */
   int32_t nt_store;     /* 1: the fill writes the matrix with non-temporal stores, 0: ordinary */
 } ht_tuning;
 

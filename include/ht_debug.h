@@ -23,6 +23,12 @@ extern "C" {
 int ht_debug_hit_values(const ht_grid* grid, const float* x, const float* y, const float* z,
                         int64_t n_hits, int32_t* info, float* vals, int32_t* slabs, void* stream);
 
+/* ht_debug_pointer_kind: how the library classifies a pointer given as a peak output, from the
+ * HIP runtime's attributes (host only, no device work): 0 = refused (not usable by a kernel,
+ * e.g. unregistered host memory), 1 = device memory, 2 = pinned host memory mapped into the
+ * device, 3 = managed memory. Errors: HT_EINVAL for NULL arguments. */
+int ht_debug_pointer_kind(const void* ptr, int32_t* kind);
+
 /* ht_fill_atomic: step 1 through the plain kernel (zero the matrix, then one global atomicAdd
  * per vote, one block per hit with its threads over the A bins, as the paper's first kernel is
  * organised). Same contract and results as ht_fill; kept as the baseline it is measured against. */
@@ -35,10 +41,12 @@ int ht_fill_atomic(const ht_grid* grid, const float* x, const float* y, const fl
 int ht_tiling(const ht_grid* grid, int32_t* rows, int32_t* n_tiles, int32_t* cand_cap,
               int32_t* lds_fill);
 
-/* ht_profile_enable: 1 turns on per-stage timing of later calls: a HIP event is recorded on the
- * call's stream before and after each stage ("prep", "fill", "fill_atomic", "candidates",
- * "peaks"); 0 turns it off. Host only; always HT_OK. */
-int ht_profile_enable(int on);
+/* ht_profile_enable: per-stage timing of later calls. mode 1: a HIP event (created without the
+ * system-scope fence) is recorded on the call's stream before and after each stage ("prep",
+ * "fill", "fill_atomic", "candidates", "peaks"); mode 2: around the fill stages only ("fill",
+ * "fill_atomic"); 0 turns it off. Graph-captured calls are not timed. Host only; HT_EINVAL for
+ * another mode. */
+int ht_profile_enable(int mode);
 
 /* ht_profile_read: waits for the recorded events of stage `name` and returns their summed
  * duration (*total_ms) and count; reset != 0 then drops all records. Errors: HT_EINVAL,

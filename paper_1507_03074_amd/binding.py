@@ -88,7 +88,8 @@ EXPORTS = ["ht_set_tuning", "ht_get_tuning", "ht_tables", "ht_fill", "ht_peaks",
            "ht_serve_create", "ht_serve_submit", "ht_serve_poll", "ht_serve_destroy",
            "ht_last_error", "ht_debug_hit_values", "ht_fill_atomic", "ht_tiling",
            "ht_profile_enable", "ht_profile_read", "ht_bench_hbm_write", "ht_bench_hbm_read",
-           "ht_bench_copy", "ht_bench_atomic_rand", "ht_bench_lds_atomic", "ht_readout"]
+           "ht_bench_copy", "ht_bench_atomic_rand", "ht_bench_lds_atomic", "ht_readout",
+           "ht_debug_pointer_kind"]
 
 _lib = None
 
@@ -119,6 +120,7 @@ def lib():
                                 ctypes.c_int),
         "ht_debug_hit_values": ([gp, vp, vp, vp, i64, vp, vp, vp, vp], ctypes.c_int),
         "ht_readout": ([gp, vp, vp, i64, vp, vp], ctypes.c_int),
+        "ht_debug_pointer_kind": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
         "ht_serve_create": ([gp, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)], ctypes.c_int),
         "ht_serve_submit": ([vp, f32p, f32p, f32p, i64, ctypes.POINTER(ctypes.c_uint64)],
                             ctypes.c_int),
@@ -285,6 +287,13 @@ def tracks_to_host(tracks, n_found, capacity):
     return tracks.cpu().numpy().view(TRACK_DTYPE)[:k].copy()
 
 
+def ht_debug_pointer_kind(ptr: int) -> int:
+    """0 refused, 1 device memory, 2 mapped pinned host memory, 3 managed (host-only query)."""
+    k = ctypes.c_int32()
+    check(lib().ht_debug_pointer_kind(ctypes.c_void_p(ptr), ctypes.byref(k)))
+    return k.value
+
+
 def ht_debug_hit_values(spec, x, y, z, stream=None):
     import torch
     g = make_grid(spec)
@@ -298,8 +307,9 @@ def ht_debug_hit_values(spec, x, y, z, stream=None):
     return info, vals, slabs
 
 
-def ht_profile_enable(on: bool):
-    return check(lib().ht_profile_enable(1 if on else 0))
+def ht_profile_enable(mode):
+    """0 / False: off; 1 / True: every stage; 2: the fill stages only."""
+    return check(lib().ht_profile_enable(int(mode)))
 
 
 def ht_profile_read(name: str, reset: bool = False):

@@ -111,7 +111,7 @@ static TuneKey tune_key(const ht_grid& g)
                  fbits(g.b_max)};
 }
 
-static const int64_t kLdsTileMax = 65536 - 8192;  // bytes of an LDS tile (room for candidates)
+static const int64_t kLdsTileMax = 65536 - 8192;  // bytes of an LDS tile (leaves room for the small scratch words)
 
 Tiling choose_tiling(const ht_grid& g)
 {
@@ -182,8 +182,8 @@ int check_tuning(const ht_grid& g, const ht_tuning& tu)
     return fail(HT_EINVAL, "tuning.rows gives too many tiles");
   if (tu.group_tiles != 0 && tu.group_tiles != 16 && tu.group_tiles != 32 && tu.group_tiles != 64)
     return fail(HT_EINVAL, "tuning.group_tiles must be 16, 32 or 64");
-  if (tu.cand_cap < 0 || (tu.cand_cap > 0 && (!pow2(tu.cand_cap) || tu.cand_cap < 2 || tu.cand_cap > 4096)))
-    return fail(HT_EINVAL, "tuning.cand_cap must be a power of two in [2, 4096]");
+  if (tu.cand_cap < 0 || (tu.cand_cap > 0 && (!pow2(tu.cand_cap) || tu.cand_cap > 4096)))
+    return fail(HT_EINVAL, "tuning.cand_cap must be a power of two <= 4096");
   if (tu.nt_store < -1 || tu.nt_store > 1) return fail(HT_EINVAL, "tuning.nt_store must be -1, 0 or 1");
   return HT_OK;
 }
@@ -285,7 +285,8 @@ size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct)
     b += al(64 * nn);                         // list
   }
   b += al(4 * (size_t)g.n_tiles);             // tile_cnt
-  b += al(8 * (size_t)g.n_tiles * g.cand_cap);  // cand
+  b += al(4 * (size_t)g.n_tiles);             // tile_off
+  b += al(8 * (size_t)g.n_tiles * g.cand_cap);  // pool
   b += al(4 * (size_t)g.n_tiles);             // tile_pk
   b += al(4 * (size_t)n_groups(g));           // group_pk
   return b;
@@ -314,7 +315,9 @@ void carve_event_scratch(const DevGrid& g, int64_t n, bool direct, char* p, EvDe
     ev->list = (float4*)take(64 * nn);
   }
   ev->tile_cnt = (uint32_t*)take(4 * (size_t)g.n_tiles);
-  ev->cand = (uint2*)take(8 * (size_t)g.n_tiles * g.cand_cap);
+  ev->tile_off = (uint32_t*)take(4 * (size_t)g.n_tiles);
+  ev->pool_cap = (uint32_t)std::min<size_t>((size_t)g.n_tiles * g.cand_cap, 0xfffffff0u);
+  ev->pool = (uint2*)take(8 * (size_t)ev->pool_cap);
   ev->tile_pk = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->group_pk = (uint32_t*)take(4 * (size_t)n_groups(g));
 }
@@ -385,8 +388,8 @@ int ensure_counters(Workspace* w, int n_ev, hipStream_t s)
 void use_counters(Workspace* w, int i, EvDesc* d)
 {
   uint32_t* pair = w->ctr + (size_t)i * (kCounterBytes / 4);
-  d->slab_cnt = pair + (w->parity[i] ? kMaxSlabs : 0);
-  d->slab_cnt_next = pair + (w->parity[i] ? 0 : kMaxSlabs);
+  d->slab_cnt = pair + (w->parity[i] ? kCounterWords : 0);
+  d->slab_cnt_next = pair + (w->parity[i] ? 0 : kCounterWords);
 }
 
 void flip_counters(Workspace* w, int n) { for (int i = 0; i < n; ++i) w->parity[i] ^= 1; }
@@ -436,7 +439,7 @@ struct ProfRec {
   hipEvent_t a, b;
 };
 static std::mutex g_prof_mu;
-static bool g_prof_on = false;
+static int g_prof_mode = 0;  // 0 off, 1 every stage, 2 the fill stages only
 static std::vector<ProfRec> g_prof;
 static std::vector<hipEvent_t> g_prof_pool;
 
@@ -449,8 +452,10 @@ static hipEvent_t prof_event()
     g_prof_pool.pop_back();
     return e;
   }
+  // timing events without the system-scope fence: they order nothing for the host, and the
+  // fence (a cache writeback) would add to what they measure
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -461,7 +466,8 @@ struct StageTimer {
   StageTimer(const char* n, hipStream_t st) : name(n), s(st)
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on || t_capturing) return;
+    if (g_prof_mode == 0 || t_capturing) return;
+    if (g_prof_mode == 2 && std::strncmp(name, "fill", 4) != 0) return;
     a = prof_event();
     if (a) (void)hipEventRecord(a, s);
   }
@@ -529,17 +535,30 @@ int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hit
 // Outputs (peak list, count) may live in device memory or in pinned host memory that is
 // mapped into the device's address space; anything else would fault on the device, so it is
 // rejected here, on the host, before any launch.
-int check_accessible(const void* ptr, const char* what)
+// 0: not usable by a kernel; 1: device memory; 2: host memory mapped into the device; 3: managed.
+// Only what the runtime positively reports as device-accessible is accepted: unregistered host
+// memory (malloc, numpy, unpinned tensors) is reported as a successful query of type
+// hipMemoryTypeUnregistered and must be refused.
+int pointer_kind(const void* ptr)
 {
-  if (!ptr) return HT_OK;
   hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
   hipError_t e = hipPointerGetAttributes(&attr, ptr);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    return fail(HT_EINVAL, "%s is neither device memory nor mapped pinned host memory", what);
+    return 0;
   }
-  if (attr.type == hipMemoryTypeHost && !attr.devicePointer)
-    return fail(HT_EINVAL, "%s is host memory without a device mapping", what);
+  if (attr.type == hipMemoryTypeDevice) return 1;
+  if (attr.type == hipMemoryTypeHost && attr.devicePointer) return 2;
+  if (attr.type == hipMemoryTypeManaged) return 3;
+  return 0;
+}
+
+int check_accessible(const void* ptr, const char* what)
+{
+  if (!ptr) return HT_OK;
+  if (pointer_kind(ptr) == 0)
+    return fail(HT_EINVAL, "%s is neither device memory nor mapped pinned host memory", what);
   return HT_OK;
 }
 
@@ -594,7 +613,9 @@ int run_event(const ht_grid* grid, const float* x, const float* y, const float* 
   if (do_peaks) {
     if (!do_fill || atomic) {
       StageTimer t("candidates", p.s);
-      if ((rc = check_launch(launch_candidates(p.g, ev, nullptr, 1, p.s), "candidate launch"))) return rc;
+      rc = check_launch(launch_candidates(p.g, ev, nullptr, 1, p.s), "candidate launch");
+      if (!do_fill) flip_counters(w, 1);
+      if (rc) return rc;
     }
     StageTimer t("peaks", p.s);
     if ((rc = check_launch(launch_peaks(p.g, ev, nullptr, 1, p.s), "peak launch"))) return rc;
@@ -824,6 +845,13 @@ int ht_readout(const ht_grid* grid, const ht_peak* peaks, const int64_t* n_found
                       "readout launch");
 }
 
+int ht_debug_pointer_kind(const void* ptr, int32_t* kind)
+{
+  if (!ptr || !kind) return fail(HT_EINVAL, "NULL argument");
+  *kind = pointer_kind(ptr);
+  return HT_OK;
+}
+
 int ht_debug_hit_values(const ht_grid* grid, const float* x, const float* y, const float* z,
                         int64_t n_hits, int32_t* info, float* vals, int32_t* slabs, void* stream)
 {
@@ -835,10 +863,11 @@ int ht_debug_hit_values(const ht_grid* grid, const float* x, const float* y, con
   return check_launch(launch_debug_hits(p.g, x, y, z, n_hits, info, vals, slabs, p.s), "debug launch");
 }
 
-int ht_profile_enable(int on)
+int ht_profile_enable(int mode)
 {
+  if (mode < 0 || mode > 2) return fail(HT_EINVAL, "profile mode must be 0, 1 or 2");
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof_on = on != 0;
+  g_prof_mode = mode;
   return HT_OK;
 }
 

@@ -16,7 +16,12 @@ constexpr int kMaxSlabs = 4096;
 // Per-event slab counters: a pair of arrays used alternately by successive calls. A call counts
 // into the array that is zero and clears the other one for the next call, so no call needs a
 // separate clearing launch. They live in memory of their own, cleared once when allocated.
-constexpr size_t kCounterBytes = 2 * sizeof(uint32_t) * kMaxSlabs;
+// Each array holds kMaxSlabs slab counters followed by the candidate-pool counter.
+constexpr int kCounterWords = kMaxSlabs + 64;
+constexpr int kPoolCounter = kMaxSlabs;
+constexpr size_t kCounterBytes = 2 * sizeof(uint32_t) * kCounterWords;
+// tile_off value of a tile whose candidates did not fit the pool (searched densely instead)
+constexpr uint32_t kTileOverflow = 0xffffffffu;
 // Direct slab lists (one fixed-capacity list per slab, capacity = the event's hit count) are
 // used while they need at most this many bytes per event; above it, a counting sort.
 constexpr size_t kDirectListMax = (size_t)1 << 29;
@@ -32,7 +37,7 @@ struct DevGrid {
   int32_t rows;            // A rows per tile; a tile is rows x n_b contiguous cells of one slab
   int32_t tiles_per_slab;  // ceil(n_a / rows)
   int32_t n_tiles;         // n_slabs * tiles_per_slab
-  int32_t cand_cap;        // candidate slots per tile (power of two)
+  int32_t cand_cap;        // candidate-pool entries per tile (the pool is shared by all tiles)
   int32_t lds_fill;        // 1: fill through an LDS tile; 0: global atomics (very wide B rows)
   int32_t group_tiles;     // tiles per workgroup of the peak search (16, 32 or 64)
   int32_t nt_store;        // 1: the fill writes the matrix with non-temporal stores
@@ -61,7 +66,9 @@ struct EvDesc {
   float4* hit_rec;      // [n_hits] (x, r2, k, 0)
   float4* list;         // hit records bucketed by slab: [n_slabs * list_cap] or [4 n_hits]
   uint32_t* tile_cnt;   // [n_tiles] candidates (cells >= threshold) per tile
-  uint2* cand;          // [n_tiles * cand_cap] (cell, votes) of the candidates, ascending per tile
+  uint32_t* tile_off;   // [n_tiles] first pool entry of each tile's candidates, or kTileOverflow
+  uint2* pool;          // [pool_cap] (cell, votes) of the candidates, ascending within a tile
+  uint32_t pool_cap;    // n_tiles * cand_cap
   uint32_t* tile_pk;    // [n_tiles] peaks per tile
   uint32_t* group_pk;   // [n_groups] peaks per group of tiles
 };

@@ -33,6 +33,7 @@ namespace {
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;
+static_assert(kBlock == 256, "candidate emission splits a tile over four wave64s");
 constexpr int kGroupTiles = 64;  // largest group of tiles per peak workgroup (g.group_tiles)
 
 __device__ __forceinline__ EvDesc load_ev(const EvDesc& ev0, const EvDesc* evs)
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_direct(DevGrid g, EvDesc ev0, c
   // clear all of the other array: an earlier call on a grid with more slabs may have used
   // entries past this grid's n_slabs
   if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < kMaxSlabs; i += kBlock) e.slab_cnt_next[i] = 0u;
+    for (int i = threadIdx.x; i < kCounterWords; i += kBlock) e.slab_cnt_next[i] = 0u;
   if ((int64_t)blockIdx.x * kBlock >= e.n_hits) return;  // uniform: whole block idle
   for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) lcnt[i] = 0u;
   __syncthreads();
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(DevGrid g, EvDesc ev0, const Ev
   // clear all of the other array: an earlier call on a grid with more slabs may have used
   // entries past this grid's n_slabs
   if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < kMaxSlabs; i += kBlock) e.slab_cnt_next[i] = 0u;
+    for (int i = threadIdx.x; i < kCounterWords; i += kBlock) e.slab_cnt_next[i] = 0u;
   if ((int64_t)blockIdx.x * kBlock >= e.n_hits) return;  // uniform: whole block idle
   for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) lcnt[i] = 0u;
   __syncthreads();
@@ -261,54 +262,60 @@ __global__ __launch_bounds__(kBlock) void k_bucket(DevGrid g, EvDesc ev0, const 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Candidates (cells >= threshold) of one tile: unordered pushes into an LDS list, then a
-// bitonic sort, so that each tile's candidates are stored by ascending cell index.
+// Candidates (cells >= threshold) of one tile, from the tile's counts in LDS: the tile reserves
+// a chunk of the event's candidate pool with one atomic, then each wave writes the candidates
+// of its quarter of the tile in cell order (ballot compaction), so every tile's chunk is sorted
+// by cell index. A tile whose candidates do not fit the pool is marked overflowed.
+// Called by the whole block; `any` is nonzero iff the tile holds a candidate (a block-uniform
+// hint from the flush; the reservation uses this function's own count); s_small: >= 9 words.
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ void push_candidate(uint32_t* s_cand, uint32_t* s_n, uint32_t cap,
-                                               uint32_t off)
+__device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uint32_t cell0,
+                                const uint32_t* s_tile, uint32_t L, uint32_t any, uint32_t* s_small)
 {
-  uint32_t p = atomicAdd(s_n, 1u);
-  if (p < cap) s_cand[p] = off;
-}
-
-__device__ void lds_sort_u32(uint32_t* s, uint32_t n)
-{
-  if (n < 2) return;
-  uint32_t P = 2;
-  while (P < n) P <<= 1;
-  for (uint32_t i = n + threadIdx.x; i < P; i += blockDim.x) s[i] = 0xffffffffu;
-  __syncthreads();
-  for (uint32_t k = 2; k <= P; k <<= 1)
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
-        uint32_t l = i ^ j;
-        if (l > i) {
-          uint32_t a = s[i], b = s[l];
-          bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            s[i] = b;
-            s[l] = a;
-          }
-        }
-      }
-      __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t T = g.threshold;
+  if (any == 0) {
+    if (threadIdx.x == 0) {
+      e.tile_cnt[tile] = 0u;
+      e.tile_off[tile] = 0u;
     }
-}
-
-// Called by the whole block after all pushes (and a barrier). `vals` holds the tile's counts
-// (the LDS tile in the fill, the matrix itself in the candidate scan).
-__device__ void finish_candidates(const DevGrid& g, const EvDesc& e, int tile, uint32_t tile_cell0,
-                                  uint32_t* s_cand, uint32_t n, const uint32_t* vals)
-{
-  if (n <= (uint32_t)g.cand_cap) {
-    lds_sort_u32(s_cand, n);
-    uint2* dst = e.cand + (size_t)tile * g.cand_cap;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-      const uint32_t off = s_cand[i];
-      dst[i] = make_uint2(tile_cell0 + off, vals[off]);
-    }
+    return;
   }
-  if (threadIdx.x == 0) e.tile_cnt[tile] = n;  // n > cand_cap marks an overflowed tile
+  const uint32_t seg = (L + 3u) / 4u;
+  const uint32_t s0 = min(L, (uint32_t)wave * seg), s1 = min(L, s0 + seg);
+  uint32_t cnt = 0;
+  for (uint32_t b = s0; b < s1; b += 64) {
+    const uint32_t i = b + lane;
+    const bool c = i < s1 && s_tile[i] >= T;
+    cnt += (uint32_t)__popcll(__ballot(c));
+  }
+  if (lane == 0) s_small[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t w0 = s_small[0], w1 = s_small[1], w2 = s_small[2];
+    const uint32_t total = w0 + w1 + w2 + s_small[3];
+    s_small[4] = 0u;
+    s_small[5] = w0;
+    s_small[6] = w0 + w1;
+    s_small[7] = w0 + w1 + w2;
+    uint32_t base = atomicAdd(&e.slab_cnt[kPoolCounter], total);
+    if (base > e.pool_cap || total > e.pool_cap - base) base = kTileOverflow;
+    s_small[8] = base;
+    e.tile_cnt[tile] = total;
+    e.tile_off[tile] = base;
+  }
+  __syncthreads();
+  const uint32_t base = s_small[8];
+  if (base == kTileOverflow) return;
+  uint32_t run = base + s_small[4 + wave];
+  for (uint32_t b = s0; b < s1; b += 64) {
+    const uint32_t i = b + lane;
+    const uint32_t v = i < s1 ? s_tile[i] : 0u;
+    const bool c = i < s1 && v >= T;
+    const uint64_t m = __ballot(c);
+    if (c) e.pool[run + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = make_uint2(cell0 + i, v);
+    run += (uint32_t)__popcll(m);
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -327,13 +334,12 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
   const uint32_t L = (uint32_t)rows * nb;
   const uint32_t Lpad = ((uint32_t)ROWS * nb + 3u) & ~3u;
   uint32_t* s_tile = smem;
-  uint32_t* s_cand = smem + Lpad;
-  uint32_t* s_ncand = s_cand + g.cand_cap;
+  uint32_t* s_small = smem + Lpad;  // 16 words
 
   u32x4* s4 = reinterpret_cast<u32x4*>(s_tile);
   const u32x4 zero4 = {0u, 0u, 0u, 0u};
   for (uint32_t i = threadIdx.x; i < Lpad / 4; i += kBlock) s4[i] = zero4;
-  if (EMIT && threadIdx.x == 0) *s_ncand = 0u;
+  if (EMIT && threadIdx.x == 0) s_small[12] = 0u;
   __syncthreads();
 
   size_t beg, end;
@@ -368,75 +374,75 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
   const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
   uint32_t* dst = e.acc + cell0;
   const uint32_t T = g.threshold;
+  uint32_t ncand = 0;
   if (VEC) {
     u32x4* d4 = reinterpret_cast<u32x4*>(dst);
     for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) {
       u32x4 v = s4[i];
       if (NT) __builtin_nontemporal_store(v, d4 + i);
       else d4[i] = v;
-      if (EMIT) {
-        uint32_t m = max(max(v.x, v.y), max(v.z, v.w));
-        if (m >= T) {
-          if (v.x >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i);
-          if (v.y >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 1);
-          if (v.z >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 2);
-          if (v.w >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 3);
-        }
-      }
+      if (EMIT)
+        ncand += (v.x >= T ? 1u : 0u) + (v.y >= T ? 1u : 0u) + (v.z >= T ? 1u : 0u) + (v.w >= T ? 1u : 0u);
     }
   } else {
     for (uint32_t i = threadIdx.x; i < L; i += kBlock) {
       uint32_t v = s_tile[i];
       if (NT) __builtin_nontemporal_store(v, dst + i);
       else dst[i] = v;
-      if (EMIT && v >= T) push_candidate(s_cand, s_ncand, g.cand_cap, i);
+      if (EMIT) ncand += v >= T ? 1u : 0u;
     }
   }
   if (EMIT) {
+    ncand = wave_sum(ncand);
+    if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_small[12], ncand);
     __syncthreads();
-    finish_candidates(g, e, tile, cell0, s_cand, *s_ncand, s_tile);
+    emit_candidates(g, e, tile, cell0, s_tile, L, s_small[12], s_small);
   }
 }
 
-// Candidates of an arbitrary matrix: one coalesced read of each tile.
+// Candidates of an arbitrary matrix: one coalesced read of each tile into LDS. Workgroup 0
+// clears the other counter array for the next call.
 template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_cand_scan(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   extern __shared__ uint32_t smem[];
   EvDesc e = load_ev(ev0, evs);
   const int tile = blockIdx.x;
+  if (tile == 0)
+    for (int i = threadIdx.x; i < kCounterWords; i += kBlock) e.slab_cnt_next[i] = 0u;
   const int slab = tile / g.tiles_per_slab;
   const int a0 = (tile - slab * g.tiles_per_slab) * g.rows;
   const int rows = min(g.rows, g.n_a - a0);
   const uint32_t nb = (uint32_t)g.n_b;
   const uint32_t L = (uint32_t)rows * nb;
-  uint32_t* s_cand = smem;
-  uint32_t* s_ncand = s_cand + g.cand_cap;
-  if (threadIdx.x == 0) *s_ncand = 0u;
+  const uint32_t Lpad = ((uint32_t)g.rows * nb + 3u) & ~3u;
+  uint32_t* s_tile = smem;
+  uint32_t* s_small = smem + Lpad;
+  if (threadIdx.x == 0) s_small[12] = 0u;
   __syncthreads();
   const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
   const uint32_t* src = e.acc + cell0;
   const uint32_t T = g.threshold;
+  uint32_t ncand = 0;
   if (VEC) {
     const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+    u32x4* l4 = reinterpret_cast<u32x4*>(s_tile);
     for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) {
-      u32x4 v = __builtin_nontemporal_load(s4 + i);
-      uint32_t m = max(max(v.x, v.y), max(v.z, v.w));
-      if (m >= T) {
-        if (v.x >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i);
-        if (v.y >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 1);
-        if (v.z >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 2);
-        if (v.w >= T) push_candidate(s_cand, s_ncand, g.cand_cap, 4 * i + 3);
-      }
+      const u32x4 v = __builtin_nontemporal_load(s4 + i);
+      l4[i] = v;
+      ncand += (v.x >= T ? 1u : 0u) + (v.y >= T ? 1u : 0u) + (v.z >= T ? 1u : 0u) + (v.w >= T ? 1u : 0u);
     }
   } else {
     for (uint32_t i = threadIdx.x; i < L; i += kBlock) {
-      uint32_t v = src[i];
-      if (v >= T) push_candidate(s_cand, s_ncand, g.cand_cap, i);
+      const uint32_t v = src[i];
+      s_tile[i] = v;
+      ncand += v >= T ? 1u : 0u;
     }
   }
+  ncand = wave_sum(ncand);
+  if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_small[12], ncand);
   __syncthreads();
-  finish_candidates(g, e, tile, cell0, s_cand, *s_ncand, src);
+  emit_candidates(g, e, tile, cell0, s_tile, L, s_small[12], s_small);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -528,16 +534,19 @@ __device__ __forceinline__ void tile_range(const DevGrid& g, int tile, uint32_t*
 }
 
 // Wave 0 of the block: s_pre = exclusive prefix over the group's tiles of counts[] (tiles whose
-// candidates overflowed count 0 when counts is tile_cnt); s_ovf marks the overflowed tiles.
-__device__ void group_prefix(const DevGrid& g, const EvDesc& e, int t0, int nt, uint32_t* s_pre,
-                             uint32_t* s_ovf, const uint32_t* counts)
+// candidates did not fit the pool count 0 when counts is tile_cnt); s_ovf marks those tiles and
+// s_off holds each tile's chunk offset in the pool.
+__device__ void group_prefix(const EvDesc& e, int t0, int nt, uint32_t* s_pre, uint32_t* s_ovf,
+                             uint32_t* s_off, const uint32_t* counts)
 {
   // tiles nt..kGroupTiles-1 count zero, so s_pre[nt..kGroupTiles] all equal the group total
   if (threadIdx.x < kGroupTiles) {
     const int i = threadIdx.x;
     uint32_t c = i < nt ? counts[t0 + i] : 0u;
-    const uint32_t ovf = i < nt && e.tile_cnt[t0 + i] > (uint32_t)g.cand_cap ? 1u : 0u;
+    const uint32_t off = i < nt ? e.tile_off[t0 + i] : 0u;
+    const uint32_t ovf = off == kTileOverflow ? 1u : 0u;
     s_ovf[i] = ovf;
+    s_off[i] = off;
     if (ovf && counts == e.tile_cnt) c = 0u;
     const uint32_t inc = wave_incl_scan(c);
     s_pre[i + 1] = inc;
@@ -557,25 +566,26 @@ __device__ __forceinline__ int group_tile_of(const uint32_t* pre, uint32_t f)
   return lo;
 }
 
-// One workgroup per group of tiles: every stored candidate of the group is tested at once
-// (thread per candidate), the peaks are compacted in order to the front of the group's
-// candidate slots, and the per-tile and per-group peak counts are written. Tiles whose
-// candidates overflowed their slots are counted by a dense pass, one wave per tile.
+// One workgroup per group of tiles: every pooled candidate of the group is tested at once
+// (thread per candidate); each tile's peaks are compacted in order to the front of its own pool
+// chunk, and the per-tile and per-group peak counts are written. Tiles whose candidates did not
+// fit the pool are counted by a dense pass, one wave per tile.
 __global__ __launch_bounds__(kBlock) void k_peak_mark(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   __shared__ uint32_t s_pre[kGroupTiles + 1];
   __shared__ uint32_t s_ovf[kGroupTiles];
+  __shared__ uint32_t s_off[kGroupTiles];
+  __shared__ uint32_t s_first[kGroupTiles];
   __shared__ uint32_t s_pk[kGroupTiles];
   __shared__ uint32_t smem[32];
   EvDesc e = load_ev(ev0, evs);
   const int t0 = blockIdx.x * g.group_tiles;
   const int nt = min(g.group_tiles, g.n_tiles - t0);
   if (threadIdx.x < kGroupTiles) s_pk[threadIdx.x] = 0u;
-  group_prefix(g, e, t0, nt, s_pre, s_ovf, e.tile_cnt);
+  group_prefix(e, t0, nt, s_pre, s_ovf, s_off, e.tile_cnt);
   __syncthreads();
   const uint32_t total = s_pre[kGroupTiles];
-  const size_t cap = (size_t)g.cand_cap;
-  uint2* region = e.cand + (size_t)t0 * cap;
+  uint2* pool = e.pool;
   const uint32_t* acc = e.acc;
   uint32_t run = 0;
   for (uint32_t base = 0; base < total; base += kBlock) {
@@ -585,15 +595,18 @@ __global__ __launch_bounds__(kBlock) void k_peak_mark(DevGrid g, EvDesc ev0, con
     int tl = 0;
     if (f < total) {
       tl = group_tile_of(s_pre, f);
-      cv = region[(size_t)tl * cap + (f - s_pre[tl])];
+      cv = pool[(size_t)s_off[tl] + (f - s_pre[tl])];
       pk = is_peak(g, acc, cv.x, cv.y);
     }
     uint32_t tot;
     const uint32_t pos = run + block_excl_scan(pk ? 1u : 0u, smem, &tot);
-    // every candidate of this chunk has been read (barriers in the scan); pos <= f, and each
-    // unread candidate sits at a slot index >= its flat index > pos, so the compaction is safe
+    // the first candidate of a tile records how many of the group's peaks precede the tile
+    if (f < total && f == s_pre[tl]) s_first[tl] = pos;
+    __syncthreads();
+    // every candidate of this chunk has been read (barriers above); a peak's rank in its tile
+    // is at most its slot, and the tile's unread candidates sit at larger slots
     if (pk) {
-      region[pos] = cv;
+      pool[(size_t)s_off[tl] + (pos - s_first[tl])] = cv;
       atomicAdd(&s_pk[tl], 1u);
     }
     run += tot;
@@ -619,13 +632,15 @@ __global__ __launch_bounds__(kBlock) void k_peak_mark(DevGrid g, EvDesc ev0, con
   if (threadIdx.x == 0) e.group_pk[blockIdx.x] = gsum;
 }
 
-// One workgroup per group: its output offset is the sum of the earlier groups' totals; the
-// group's staged peaks are copied out in order, overflowed tiles are re-scanned densely.
+// One workgroup per group: its output offset is the sum of the earlier groups' totals; each
+// tile's compacted peaks are copied out of its pool chunk in order, tiles that did not fit the
+// pool are re-scanned densely.
 __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   __shared__ uint32_t s_out[kGroupTiles + 1];
   __shared__ uint32_t s_stg[kGroupTiles + 1];
   __shared__ uint32_t s_ovf[kGroupTiles];
+  __shared__ uint32_t s_off[kGroupTiles];
   __shared__ uint32_t smem[32];
   EvDesc e = load_ev(ev0, evs);
   const int G = blockIdx.x;
@@ -637,9 +652,9 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
   const int64_t base = (int64_t)base32;
   if (G == (int)gridDim.x - 1 && threadIdx.x == 0) *e.n_found = base + e.group_pk[G];
   if (base >= e.cap) return;  // uniform
-  group_prefix(g, e, t0, nt, s_out, s_ovf, e.tile_pk);
+  group_prefix(e, t0, nt, s_out, s_ovf, s_off, e.tile_pk);
   __syncthreads();
-  // staged prefix: peaks of the tiles that were not overflowed
+  // staged prefix: peaks of the tiles held in the pool
   if (threadIdx.x < kGroupTiles) {
     const int i = threadIdx.x;
     const uint32_t c = (i < nt && !s_ovf[i]) ? e.tile_pk[t0 + i] : 0u;
@@ -649,12 +664,12 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
   }
   __syncthreads();
   const uint32_t staged = s_stg[kGroupTiles];
-  const uint2* region = e.cand + (size_t)t0 * (size_t)g.cand_cap;
   for (uint32_t j = threadIdx.x; j < staged; j += kBlock) {
     const int tl = group_tile_of(s_stg, j);
-    const int64_t o = base + s_out[tl] + (j - s_stg[tl]);
+    const uint32_t i = j - s_stg[tl];
+    const int64_t o = base + s_out[tl] + i;
     if (o < e.cap) {
-      const uint2 cv = region[j];
+      const uint2 cv = e.pool[(size_t)s_off[tl] + i];
       ht_peak pk;
       pk.cell = cv.x;
       pk.votes = cv.y;
@@ -816,7 +831,7 @@ int n_groups(const DevGrid& g) { return (g.n_tiles + g.group_tiles - 1) / g.grou
 size_t fill_lds_bytes(const DevGrid& g)
 {
   const size_t lpad = (((size_t)g.rows * g.n_b) + 3) & ~(size_t)3;
-  return (lpad + (size_t)g.cand_cap + 4) * sizeof(uint32_t);
+  return (lpad + 16) * sizeof(uint32_t);
 }
 
 hipError_t launch_prep(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
@@ -844,7 +859,7 @@ hipError_t launch_fill(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, i
 hipError_t launch_candidates(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                              hipStream_t s)
 {
-  const size_t lds = ((size_t)g.cand_cap + 4) * sizeof(uint32_t);
+  const size_t lds = fill_lds_bytes(g);
   dim3 grid(g.n_tiles, n_ev);
   if (g.n_b % 4 == 0) hipLaunchKernelGGL(k_cand_scan<true>, grid, dim3(kBlock), lds, s, g, ev0, evs);
   else hipLaunchKernelGGL(k_cand_scan<false>, grid, dim3(kBlock), lds, s, g, ev0, evs);

@@ -134,8 +134,8 @@ int launch(ht_server* sv, Batch& b)
     EvDesc& d = sv->h_ev[b.stream][i];
     std::memset(&d, 0, sizeof(d));
     carve_event_scratch(sv->g, mh, sv->direct, sl.scratch, &d);
-    d.slab_cnt = sl.ctr + (sl.parity ? kMaxSlabs : 0);
-    d.slab_cnt_next = sl.ctr + (sl.parity ? 0 : kMaxSlabs);
+    d.slab_cnt = sl.ctr + (sl.parity ? kCounterWords : 0);
+    d.slab_cnt_next = sl.ctr + (sl.parity ? 0 : kCounterWords);
     sl.parity ^= 1;
     d.x = sl.hits;
     d.y = sl.hits + r->n;

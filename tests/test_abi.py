@@ -145,3 +145,11 @@ def test_tuning_validated_and_applied_on_host(lib):
     finally:
         B.ht_set_tuning(spec)
     assert B.ht_get_tuning(spec).as_dict() == default
+
+
+def test_profile_modes_validated_on_host(lib):
+    for mode in (1, 2, 0):
+        assert lib.ht_profile_enable(mode) == 0
+    for mode in (-1, 3):
+        assert lib.ht_profile_enable(mode) == B.HT_EINVAL
+    assert lib.ht_profile_enable(0) == 0

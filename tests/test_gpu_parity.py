@@ -538,15 +538,23 @@ def test_peaks_written_to_pinned_host_memory(gpu):
         assert int(h_nf[0]) == on
         got = h_out.numpy().view(np.uint32)[:on]
         assert np.array_equal(got[:, 0], oc) and np.array_equal(got[:, 1], ov)
-    # ordinary (unpinned) host memory is refused on the host, before any launch
-    plain = torch.zeros((cap, 2), dtype=torch.int32)
-    g = B.make_grid(CFG0)
-    rc = B.lib().ht_fill_peaks(ctypes.byref(g), ctypes.c_void_p(xd.data_ptr()),
-                               ctypes.c_void_p(yd.data_ptr()), ctypes.c_void_p(zd.data_ptr()),
-                               xd.numel(), ctypes.c_void_p(acc.data_ptr()),
-                               ctypes.c_void_p(plain.data_ptr()), cap,
-                               ctypes.c_void_p(h_nf.data_ptr()), None)
-    assert rc == B.HT_EINVAL
+
+
+def test_output_pointer_classification(gpu):
+    """The host-side check that guards the peak outputs: device memory and mapped pinned host
+    memory are accepted, unregistered host memory is refused. Only the classification is
+    queried here (host only); no kernel is ever given a refused pointer."""
+    import torch
+    B = gpu
+    dev = torch.zeros(16, dtype=torch.int32, device="cuda")
+    pinned = torch.zeros(16, dtype=torch.int32, pin_memory=True)
+    plain = torch.zeros(16, dtype=torch.int32)
+    arr = np.zeros(16, np.int32)
+    assert B.ht_debug_pointer_kind(dev.data_ptr()) == 1
+    assert B.ht_debug_pointer_kind(pinned.data_ptr()) == 2
+    assert B.ht_debug_pointer_kind(pinned.data_ptr() + 8) == 2
+    assert B.ht_debug_pointer_kind(plain.data_ptr()) == 0
+    assert B.ht_debug_pointer_kind(arr.ctypes.data) == 0
 
 
 def test_alternating_grid_sizes_keep_counters_clean(gpu):
