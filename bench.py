@@ -303,6 +303,30 @@ def bench_transfers(B, torch, synth, spec, sizes=(500, 1000, 2000, 4000, 8000), 
     return res
 
 
+def counter_traffic(tuning: dict):
+    """HBM bytes per fill launch from the committed FETCH_SIZE / WRITE_SIZE counter summary
+    (each counter scaled by what it reads for a copy of known size), or None when the summary
+    was taken on other kernel sources or another launch shape."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_fill_paper-event_counters.md")
+    src = os.path.join(ROOT, "paper_1507_03074_amd", "csrc", "ht_kernels.hip")
+    try:
+        text = open(path).read()
+        m = re.search(r"```json\n(.*?)\n```", text, re.S)
+        rec = json.loads(m.group(1))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    shape = "%d,%d,%d,%d" % (tuning["rows"], tuning["group_tiles"], tuning["cand_cap"], tuning["nt_store"])
+    if rec.get("kernels_source_sha256") != sha or rec.get("tuning") != shape:
+        return None
+    for name, v in rec["per_launch"].items():
+        if name.startswith("k_fill<%d," % tuning["rows"]):
+            return v["traffic_bytes"]
+    return None
+
+
 def ctypes_stream(stream):
     import ctypes
     return ctypes.c_void_p(stream.cuda_stream)
@@ -318,6 +342,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="main line only (no extra workloads)")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
+    ap.add_argument("--tuning", default=None,
+                    help="rows,group_tiles,cand_cap,nt_store: this launch shape instead of autotuning")
+    ap.add_argument("--counters", action="store_true",
+                    help="for hardware-counter runs: a 256 MiB copy (the byte-counter reference) "
+                         "three times, then --steps steps untimed; prints one line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -351,9 +380,28 @@ def main():
         x, y, z = dev_hits[i]
         B.ht_fill_peaks(spec, x, y, z, acc, h_out[i], cap, h_nf[i:i + 1], stream)
 
+    if args.counters:
+        if args.tuning:
+            B.ht_set_tuning(spec, B.Tuning(*[int(v) for v in args.tuning.split(",")]))
+        copy_bytes = 256 << 20
+        src = torch.zeros(copy_bytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            B.check(B.lib().ht_bench_copy(dst.data_ptr(), src.data_ptr(), copy_bytes, ctypes_stream(stream)))
+        torch.cuda.synchronize()
+        for k in range(args.steps):
+            step(k)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": True, "copy_bytes": copy_bytes, "copies": 3,
+                          "steps": args.steps, "tuning": B.ht_get_tuning(spec).as_dict()}), flush=True)
+        return
+
     # launch shape from the autotuner (every candidate is gated on bit-exact results)
     tuned = None
-    if not args.no_tune:
+    if args.tuning:
+        B.ht_set_tuning(spec, B.Tuning(*[int(v) for v in args.tuning.split(",")]))
+        tuned = {"given": args.tuning}
+    elif not args.no_tune:
         from paper_1507_03074_amd import tune
         log("autotuning the launch shape")
         rep = tune.autotune(spec, [(e.x, e.y, e.z) for e in evs[:4]], reps=30)
@@ -446,8 +494,10 @@ def main():
         "stage_ms_events_every_stage": stage,
         "ms_per_step_without_events": round(1000.0 * (t3 - t2) / n_extra, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_fill", "alg_bytes_per_launch": alg_bytes},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counter_traffic(B.ht_get_tuning(spec).as_dict()),
+                     "kernel": "k_fill", "alg_bytes_per_launch": alg_bytes,
+                     "fill_kernel_us": round(fill_avg_s * 1e6, 2)},
         "peaks_per_event": round(float(np.mean(nfound)), 1),
         "tuning": B.ht_get_tuning(spec).as_dict(),
         "autotune": tuned,
