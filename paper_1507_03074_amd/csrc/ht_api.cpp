@@ -255,6 +255,9 @@ DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
   d.lds_fill = tl.lds_fill;
   d.group_tiles = tl.group_tiles;
   d.nt_store = tl.nt_store;
+  // candidate test: enough workgroups to spread a few thousand candidates over the whole chip
+  // in one pass (two candidates per wave), few enough that a near-empty event exits at once
+  d.test_blocks = std::max(16, std::min(1024, (tl.n_tiles + 15) / 16));
   d.a2 = t.a2;
   d.phi_cs = t.phi;
   d.th_cs = t.th;
@@ -287,6 +290,8 @@ size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct)
   b += al(4 * (size_t)g.n_tiles);             // tile_cnt
   b += al(4 * (size_t)g.n_tiles);             // tile_off
   b += al(8 * (size_t)g.n_tiles * g.cand_cap);  // pool
+  b += al((size_t)g.n_tiles * g.cand_cap);      // pk_flag
+  b += al(4 * (size_t)g.n_tiles);               // ovf_list
   b += al(4 * (size_t)g.n_tiles);             // tile_pk
   b += al(4 * (size_t)n_groups(g));           // group_pk
   return b;
@@ -318,6 +323,8 @@ void carve_event_scratch(const DevGrid& g, int64_t n, bool direct, char* p, EvDe
   ev->tile_off = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->pool_cap = (uint32_t)std::min<size_t>((size_t)g.n_tiles * g.cand_cap, 0xfffffff0u);
   ev->pool = (uint2*)take(8 * (size_t)ev->pool_cap);
+  ev->pk_flag = (uint8_t*)take((size_t)ev->pool_cap);
+  ev->ovf_list = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->tile_pk = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->group_pk = (uint32_t*)take(4 * (size_t)n_groups(g));
 }

@@ -16,9 +16,13 @@ constexpr int kMaxSlabs = 4096;
 // Per-event slab counters: a pair of arrays used alternately by successive calls. A call counts
 // into the array that is zero and clears the other one for the next call, so no call needs a
 // separate clearing launch. They live in memory of their own, cleared once when allocated.
-// Each array holds kMaxSlabs slab counters followed by the candidate-pool counter.
+// Each array holds kMaxSlabs slab counters followed by the candidate-pool cursor, the marker
+// of the one pool reservation that crosses the pool's end (pool_cap + 1 - its start, 0 if
+// none) and the number of tiles whose candidates did not fit.
 constexpr int kCounterWords = kMaxSlabs + 64;
 constexpr int kPoolCounter = kMaxSlabs;
+constexpr int kPoolCut = kMaxSlabs + 1;
+constexpr int kOvfCounter = kMaxSlabs + 2;
 constexpr size_t kCounterBytes = 2 * sizeof(uint32_t) * kCounterWords;
 // tile_off value of a tile whose candidates did not fit the pool (searched densely instead)
 constexpr uint32_t kTileOverflow = 0xffffffffu;
@@ -41,6 +45,7 @@ struct DevGrid {
   int32_t lds_fill;        // 1: fill through an LDS tile; 0: global atomics (very wide B rows)
   int32_t group_tiles;     // tiles per workgroup of the peak search (16, 32 or 64)
   int32_t nt_store;        // 1: the fill writes the matrix with non-temporal stores
+  int32_t test_blocks;     // workgroups per event of the candidate test
   const float* a2;         // device [n_a]
   const float* phi_cs;     // device [2 * 2 n_phi] (cos, sin)
   const float* th_cs;      // device [2 * (2 n_theta + 1)] (cos, sin)
@@ -69,6 +74,8 @@ struct EvDesc {
   uint32_t* tile_off;   // [n_tiles] first pool entry of each tile's candidates, or kTileOverflow
   uint2* pool;          // [pool_cap] (cell, votes) of the candidates, ascending within a tile
   uint32_t pool_cap;    // n_tiles * cand_cap
+  uint8_t* pk_flag;     // [pool_cap] 1 if the pool entry is a peak
+  uint32_t* ovf_list;   // [n_tiles] tiles whose candidates did not fit the pool
   uint32_t* tile_pk;    // [n_tiles] peaks per tile
   uint32_t* group_pk;   // [n_groups] peaks per group of tiles
 };

@@ -274,6 +274,11 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
 {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t T = g.threshold;
+  if (threadIdx.x == 0) {
+    // peak counts start at zero; the candidate test (a later launch) adds to them
+    e.tile_pk[tile] = 0u;
+    if (tile % g.group_tiles == 0) e.group_pk[tile / g.group_tiles] = 0u;
+  }
   if (any == 0) {
     if (threadIdx.x == 0) {
       e.tile_cnt[tile] = 0u;
@@ -299,7 +304,13 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
     s_small[6] = w0 + w1;
     s_small[7] = w0 + w1 + w2;
     uint32_t base = atomicAdd(&e.slab_cnt[kPoolCounter], total);
-    if (base > e.pool_cap || total > e.pool_cap - base) base = kTileOverflow;
+    if (base > e.pool_cap || total > e.pool_cap - base) {
+      // reservations are contiguous, so at most one starts inside the pool and crosses its
+      // end: it marks where the written entries stop
+      if (base <= e.pool_cap) e.slab_cnt[kPoolCut] = e.pool_cap - base + 1u;
+      e.ovf_list[atomicAdd(&e.slab_cnt[kOvfCounter], 1u)] = (uint32_t)tile;
+      base = kTileOverflow;
+    }
     s_small[8] = base;
     e.tile_cnt[tile] = total;
     e.tile_off[tile] = base;
@@ -566,81 +577,129 @@ __device__ __forceinline__ int group_tile_of(const uint32_t* pre, uint32_t f)
   return lo;
 }
 
-// One workgroup per group of tiles: every pooled candidate of the group is tested at once
-// (thread per candidate); each tile's peaks are compacted in order to the front of its own pool
-// chunk, and the per-tile and per-group peak counts are written. Tiles whose candidates did not
-// fit the pool are counted by a dense pass, one wave per tile.
-__global__ __launch_bounds__(kBlock) void k_peak_mark(DevGrid g, EvDesc ev0, const EvDesc* evs)
+// Whether any cell of neighbour row k (0..26: dt, dp, da in {-1, 0, 1}, row-major) of candidate
+// c with v votes beats it under (votes, -index). Rows outside theta or A are absent; phi wraps.
+// Loads one 12-byte window of three cells; the window of a row starts at
+// min(max(b, 1) - 1, n_b - 3), so it stays inside the row.
+__device__ bool row_beats(const DevGrid& g, const uint32_t* __restrict__ acc, uint32_t c, uint32_t v, int k)
 {
-  __shared__ uint32_t s_pre[kGroupTiles + 1];
-  __shared__ uint32_t s_ovf[kGroupTiles];
-  __shared__ uint32_t s_off[kGroupTiles];
-  __shared__ uint32_t s_first[kGroupTiles];
-  __shared__ uint32_t s_pk[kGroupTiles];
-  __shared__ uint32_t smem[32];
-  EvDesc e = load_ev(ev0, evs);
-  const int t0 = blockIdx.x * g.group_tiles;
-  const int nt = min(g.group_tiles, g.n_tiles - t0);
-  if (threadIdx.x < kGroupTiles) s_pk[threadIdx.x] = 0u;
-  group_prefix(e, t0, nt, s_pre, s_ovf, s_off, e.tile_cnt);
-  __syncthreads();
-  const uint32_t total = s_pre[kGroupTiles];
-  uint2* pool = e.pool;
-  const uint32_t* acc = e.acc;
-  uint32_t run = 0;
-  for (uint32_t base = 0; base < total; base += kBlock) {
-    const uint32_t f = base + threadIdx.x;
-    bool pk = false;
-    uint2 cv = make_uint2(0u, 0u);
-    int tl = 0;
-    if (f < total) {
-      tl = group_tile_of(s_pre, f);
-      cv = pool[(size_t)s_off[tl] + (f - s_pre[tl])];
-      pk = is_peak(g, acc, cv.x, cv.y);
+  const uint32_t nb = (uint32_t)g.n_b, na = (uint32_t)g.n_a, np = (uint32_t)g.n_phi;
+  uint32_t t, p, a, b;
+  cell_coords(g, c, &t, &p, &a, &b);
+  const int dt = k / 9 - 1, dp = (k / 3) % 3 - 1, da = k % 3 - 1;
+  const int tt = (int)t + dt, aa = (int)a + da;
+  if (tt < 0 || tt >= g.n_theta || aa < 0 || aa >= (int)na) return false;
+  const uint32_t pp = dp < 0 ? (p == 0 ? np - 1 : p - 1) : (dp > 0 ? (p + 1 == np ? 0 : p + 1) : p);
+  const uint32_t rowc = (((uint32_t)tt * np + pp) * na + (uint32_t)aa) * nb;
+  const bool centre_row = k == 13;
+  if (nb < 3) {
+    bool beaten = false;
+    for (uint32_t bb = b == 0 ? 0 : b - 1; bb <= b + 1 && bb < nb; ++bb) {
+      if (centre_row && bb == b) continue;
+      const uint32_t n = rowc + bb;
+      const uint32_t w = acc[n];
+      beaten |= w > v || (w == v && n < c);
     }
-    uint32_t tot;
-    const uint32_t pos = run + block_excl_scan(pk ? 1u : 0u, smem, &tot);
-    // the first candidate of a tile records how many of the group's peaks precede the tile
-    if (f < total && f == s_pre[tl]) s_first[tl] = pos;
-    __syncthreads();
-    // every candidate of this chunk has been read (barriers above); a peak's rank in its tile
-    // is at most its slot, and the tile's unread candidates sit at larger slots
-    if (pk) {
-      pool[(size_t)s_off[tl] + (pos - s_first[tl])] = cv;
-      atomicAdd(&s_pk[tl], 1u);
-    }
-    run += tot;
-    __syncthreads();
+    return beaten;
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int tl = wave; tl < nt; tl += kBlock / 64) {
-    if (!s_ovf[tl]) continue;
+  const uint32_t w0 = min(max(b, 1u) - 1u, nb - 3u);
+  const U32x3 row = *reinterpret_cast<const U32x3*>(acc + rowc + w0);
+  const uint32_t vals[3] = {row.v0, row.v1, row.v2};
+  bool beaten = false;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint32_t bb = w0 + (uint32_t)q;
+    const bool near = bb + 1u >= b && bb <= b + 1u && !(centre_row && bb == b);
+    const uint32_t n = rowc + bb;
+    beaten |= near && (vals[q] > v || (vals[q] == v && n < c));
+  }
+  return beaten;
+}
+
+__device__ __forceinline__ void count_peak(const DevGrid& g, const EvDesc& e, uint32_t c)
+{
+  const uint32_t nb = (uint32_t)g.n_b;
+  const uint32_t slab_cells = (uint32_t)g.n_a * nb;
+  const uint32_t slab = c / slab_cells;
+  const uint32_t a = (c - slab * slab_cells) / nb;
+  const uint32_t tile = slab * (uint32_t)g.tiles_per_slab + a / (uint32_t)g.rows;
+  atomicAdd(&e.tile_pk[tile], 1u);
+  atomicAdd(&e.group_pk[tile / (uint32_t)g.group_tiles], 1u);
+}
+
+// Peak test of every pooled candidate, spread evenly over the grid whatever tiles they came
+// from. Few candidates (at most two passes of the grid): half a wave (32 lanes) per candidate,
+// one lane per neighbour row, so a candidate costs one load per lane and a ballot, and the
+// whole test is about one memory round trip. Many candidates: one thread per candidate, its 27
+// row loads issued back to back. Each result goes to pk_flag; a peak adds one to its tile's and
+// its group's counts. Tiles whose candidates did not fit the pool are counted densely, one wave
+// per tile.
+__global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  EvDesc e = load_ev(ev0, evs);
+  const uint32_t cut = e.slab_cnt[kPoolCut];
+  const uint32_t n_valid = min(cut ? e.pool_cap + 1u - cut : e.slab_cnt[kPoolCounter], e.pool_cap);
+  const int lane = threadIdx.x & 63, half = lane >> 5, k = lane & 31;
+  const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const uint32_t n_waves = gridDim.x * (kBlock / 64);
+  const uint32_t* acc = e.acc;
+  if (n_valid <= 4u * n_waves) {
+    for (uint32_t i0 = 2u * wave; i0 < n_valid; i0 += 2u * n_waves) {  // wave-uniform
+      const uint32_t i = i0 + (uint32_t)half;
+      const bool live = i < n_valid;
+      uint2 cv = make_uint2(0u, 0u);
+      bool beaten = false;
+      if (live) {
+        cv = e.pool[i];
+        if (k < 27) beaten = row_beats(g, acc, cv.x, cv.y, k);
+      }
+      const uint64_t m = __ballot(beaten);
+      const uint32_t hm = (uint32_t)(m >> (32 * half));
+      if (live && k == 0) {
+        const bool pk = hm == 0u;
+        e.pk_flag[i] = pk ? 1 : 0;
+        if (pk) count_peak(g, e, cv.x);
+      }
+    }
+  } else {
+    const uint32_t n_threads = gridDim.x * kBlock;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n_valid; i += n_threads) {
+      const uint2 cv = e.pool[i];
+      const bool pk = is_peak(g, acc, cv.x, cv.y);
+      e.pk_flag[i] = pk ? 1 : 0;
+      if (pk) count_peak(g, e, cv.x);
+    }
+  }
+  const uint32_t n_ovf = e.slab_cnt[kOvfCounter];
+  for (uint32_t j = wave; j < n_ovf; j += n_waves) {
+    const int tile = (int)e.ovf_list[j];
     uint32_t cell0, L;
-    tile_range(g, t0 + tl, &cell0, &L);
+    tile_range(g, tile, &cell0, &L);
     uint32_t mine = 0;
-    for (uint32_t i = lane; i < L; i += 64) {
-      const uint32_t c = cell0 + i;
+    for (uint32_t q = (uint32_t)lane; q < L; q += 64) {
+      const uint32_t c = cell0 + q;
       const uint32_t v = acc[c];
       if (v >= g.threshold && is_peak(g, acc, c, v)) ++mine;
     }
     mine = wave_sum(mine);
-    if (lane == 0) s_pk[tl] = mine;
+    if (lane == 0 && mine) {
+      atomicAdd(&e.tile_pk[tile], mine);
+      atomicAdd(&e.group_pk[tile / g.group_tiles], mine);
+    }
   }
-  __syncthreads();
-  if ((int)threadIdx.x < nt) e.tile_pk[t0 + threadIdx.x] = s_pk[threadIdx.x];
-  const uint32_t gsum = block_sum(threadIdx.x < kGroupTiles ? s_pk[threadIdx.x] : 0u, smem);
-  if (threadIdx.x == 0) e.group_pk[blockIdx.x] = gsum;
 }
 
-// One workgroup per group: its output offset is the sum of the earlier groups' totals; each
-// tile's compacted peaks are copied out of its pool chunk in order, tiles that did not fit the
-// pool are re-scanned densely.
+// One workgroup per group of tiles: its output offset is the sum of the earlier groups' peak
+// counts; the group's pooled candidates are walked in order (tile by tile, each tile's chunk
+// ascending) and the flagged ones written out; tiles that did not fit the pool are re-scanned
+// densely.
 __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
+  __shared__ uint32_t s_pre[kGroupTiles + 1];
   __shared__ uint32_t s_out[kGroupTiles + 1];
-  __shared__ uint32_t s_stg[kGroupTiles + 1];
   __shared__ uint32_t s_ovf[kGroupTiles];
   __shared__ uint32_t s_off[kGroupTiles];
+  __shared__ uint32_t s_first[kGroupTiles];
   __shared__ uint32_t smem[32];
   EvDesc e = load_ev(ev0, evs);
   const int G = blockIdx.x;
@@ -652,29 +711,44 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
   const int64_t base = (int64_t)base32;
   if (G == (int)gridDim.x - 1 && threadIdx.x == 0) *e.n_found = base + e.group_pk[G];
   if (base >= e.cap) return;  // uniform
-  group_prefix(e, t0, nt, s_out, s_ovf, s_off, e.tile_pk);
-  __syncthreads();
-  // staged prefix: peaks of the tiles held in the pool
-  if (threadIdx.x < kGroupTiles) {
-    const int i = threadIdx.x;
-    const uint32_t c = (i < nt && !s_ovf[i]) ? e.tile_pk[t0 + i] : 0u;
+  group_prefix(e, t0, nt, s_pre, s_ovf, s_off, e.tile_cnt);
+  if (threadIdx.x >= 64 && threadIdx.x < 64 + kGroupTiles) {
+    // second wave: prefix of the peak counts of all the group's tiles
+    const int i = threadIdx.x - 64;
+    const uint32_t c = i < nt ? e.tile_pk[t0 + i] : 0u;
     const uint32_t inc = wave_incl_scan(c);
-    s_stg[i + 1] = inc;
-    if (i == 0) s_stg[0] = 0u;
+    s_out[i + 1] = inc;
+    if (i == 0) s_out[0] = 0u;
   }
   __syncthreads();
-  const uint32_t staged = s_stg[kGroupTiles];
-  for (uint32_t j = threadIdx.x; j < staged; j += kBlock) {
-    const int tl = group_tile_of(s_stg, j);
-    const uint32_t i = j - s_stg[tl];
-    const int64_t o = base + s_out[tl] + i;
-    if (o < e.cap) {
-      const uint2 cv = e.pool[(size_t)s_off[tl] + i];
-      ht_peak pk;
-      pk.cell = cv.x;
-      pk.votes = cv.y;
-      e.out[o] = pk;
+  const uint32_t total = s_pre[kGroupTiles];
+  uint32_t run = 0;
+  for (uint32_t b0 = 0; b0 < total; b0 += kBlock) {
+    const uint32_t f = b0 + threadIdx.x;
+    bool pk = false;
+    int tl = 0;
+    size_t idx = 0;
+    if (f < total) {
+      tl = group_tile_of(s_pre, f);
+      idx = (size_t)s_off[tl] + (f - s_pre[tl]);
+      pk = e.pk_flag[idx] != 0;
     }
+    uint32_t tot;
+    const uint32_t pos = run + block_excl_scan(pk ? 1u : 0u, smem, &tot);
+    // the first candidate of a tile records how many of the group's pooled peaks precede it
+    if (f < total && f == s_pre[tl]) s_first[tl] = pos;
+    __syncthreads();
+    if (pk) {
+      const int64_t o = base + s_out[tl] + (pos - s_first[tl]);
+      if (o < e.cap) {
+        const uint2 cv = e.pool[idx];
+        ht_peak q;
+        q.cell = cv.x;
+        q.votes = cv.y;
+        e.out[o] = q;
+      }
+    }
+    run += tot;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t* acc = e.acc;
@@ -682,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
     if (!s_ovf[tl]) continue;
     uint32_t cell0, L;
     tile_range(g, t0 + tl, &cell0, &L);
-    uint32_t run = 0;
+    uint32_t r = 0;
     for (uint32_t b0 = 0; b0 < L; b0 += 64) {
       const uint32_t i = b0 + lane;
       bool pk = false;
@@ -693,14 +767,14 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
         pk = v >= g.threshold && is_peak(g, acc, c, v);
       }
       const uint64_t m = __ballot(pk);
-      const int64_t o = base + s_out[tl] + run + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      const int64_t o = base + s_out[tl] + r + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
       if (pk && o < e.cap) {
         ht_peak q;
         q.cell = c;
         q.votes = v;
         e.out[o] = q;
       }
-      run += (uint32_t)__popcll(m);
+      r += (uint32_t)__popcll(m);
     }
   }
 }
@@ -869,9 +943,8 @@ hipError_t launch_candidates(const DevGrid& g, const EvDesc& ev0, const EvDesc* 
 hipError_t launch_peaks(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                         hipStream_t s)
 {
-  dim3 grid(n_groups(g), n_ev);
-  hipLaunchKernelGGL(k_peak_mark, grid, dim3(kBlock), 0, s, g, ev0, evs);
-  hipLaunchKernelGGL(k_peak_write, grid, dim3(kBlock), 0, s, g, ev0, evs);
+  hipLaunchKernelGGL(k_peak_test, dim3(g.test_blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
+  hipLaunchKernelGGL(k_peak_write, dim3(n_groups(g), n_ev), dim3(kBlock), 0, s, g, ev0, evs);
   return hipGetLastError();
 }
 
