@@ -357,7 +357,7 @@ def counter_traffic(tuning: dict):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, AttributeError, ValueError):
         return None
-    shape = "%d,%d,%d,%d" % (tuning["rows"], tuning["group_tiles"], tuning["cand_cap"], tuning["nt_store"])
+    shape = ",".join(str(tuning[f]) for f in ("rows", "group_tiles", "cand_cap", "nt_store", "tiles_per_block"))
     if rec.get("kernels_source_sha256") != sha or rec.get("tuning") != shape:
         return None
     for name, v in rec["per_launch"].items():
@@ -382,7 +382,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="main line only (no extra workloads)")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
     ap.add_argument("--tuning", default=None,
-                    help="rows,group_tiles,cand_cap,nt_store: this launch shape instead of autotuning")
+                    help="rows,group_tiles,cand_cap,nt_store,tiles_per_block: this launch shape "
+                         "instead of autotuning")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: a 256 MiB copy (the byte-counter reference) "
                          "three times, then --steps steps untimed; prints one line")

@@ -95,7 +95,11 @@ typedef struct ht_tuning {
                            at or above the threshold of all tiles share a pool of
                            n_tiles * cand_cap entries; tiles that do not fit are searched
                            densely (slower, same results) */
-  int32_t nt_store;     /* 1: the fill writes the matrix with non-temporal stores, 0: ordinary */
+  int32_t nt_store;     /* store kind of the fill's single write of the matrix: 0 ordinary
+                           16-byte stores, 1 non-temporal 16-byte stores, 2 ordinary 4-byte
+                           stores */
+  int32_t tiles_per_block; /* fill tiles per workgroup, filled in turn with one LDS tile (the
+                              slab's hit records are read once): a power of two <= 64 */
 } ht_tuning;
 
 /* ht_set_tuning: use `tuning` for every later call on grids with these dimensions and ranges

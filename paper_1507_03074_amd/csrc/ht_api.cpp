@@ -87,7 +87,7 @@ void host_tables(const ht_grid& g, std::vector<float>& a2, float& inv_db, std::v
 // Tiling
 // ---------------------------------------------------------------------------------------------
 struct Tiling {
-  int32_t rows, tiles_per_slab, n_tiles, cand_cap, lds_fill, group_tiles, nt_store;
+  int32_t rows, tiles_per_slab, n_tiles, cand_cap, lds_fill, group_tiles, nt_store, fill_tiles;
 };
 
 static int env_int(const char* name, int def)
@@ -148,7 +148,13 @@ Tiling choose_tiling(const ht_grid& g)
   const int forced_gt = env_int("HT_GROUP_TILES", 0);
   if (forced_gt == 16 || forced_gt == 32 || forced_gt == 64) gt = forced_gt;
   t.group_tiles = gt;
-  t.nt_store = env_int("HT_FILL_NT", 0) ? 1 : 0;
+  t.nt_store = std::min(2, std::max(0, env_int("HT_FILL_NT", 0)));
+  // fill tiles per workgroup: one by default (measured fastest on the paper grid: many short
+  // workgroups hide the record-load latency better than fewer workgroups looping over tiles)
+  int ft = 1;
+  const int forced_ft = env_int("HT_FILL_TILES", 0);
+  if (forced_ft > 0 && forced_ft <= 64 && (forced_ft & (forced_ft - 1)) == 0) ft = forced_ft;
+  t.fill_tiles = ft;
   ht_tuning tu;
   bool have = false;
   {
@@ -164,6 +170,7 @@ Tiling choose_tiling(const ht_grid& g)
     if (tu.group_tiles > 0) t.group_tiles = tu.group_tiles;
     if (tu.cand_cap > 0) t.cand_cap = tu.cand_cap;
     if (tu.nt_store >= 0) t.nt_store = tu.nt_store;
+    if (tu.tiles_per_block > 0) t.fill_tiles = tu.tiles_per_block;
     t.tiles_per_slab = (g.n_a + t.rows - 1) / t.rows;
     t.n_tiles = g.n_theta * g.n_phi * t.tiles_per_slab;
   }
@@ -184,7 +191,9 @@ int check_tuning(const ht_grid& g, const ht_tuning& tu)
     return fail(HT_EINVAL, "tuning.group_tiles must be 16, 32 or 64");
   if (tu.cand_cap < 0 || (tu.cand_cap > 0 && (!pow2(tu.cand_cap) || tu.cand_cap > 4096)))
     return fail(HT_EINVAL, "tuning.cand_cap must be a power of two <= 4096");
-  if (tu.nt_store < -1 || tu.nt_store > 1) return fail(HT_EINVAL, "tuning.nt_store must be -1, 0 or 1");
+  if (tu.nt_store < -1 || tu.nt_store > 2) return fail(HT_EINVAL, "tuning.nt_store must be -1, 0, 1 or 2");
+  if (tu.tiles_per_block < 0 || (tu.tiles_per_block > 0 && (!pow2(tu.tiles_per_block) || tu.tiles_per_block > 64)))
+    return fail(HT_EINVAL, "tuning.tiles_per_block must be a power of two <= 64");
   return HT_OK;
 }
 
@@ -239,6 +248,7 @@ int get_tables(const ht_grid& g, int dev, DevTables* out)
 DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
 {
   DevGrid d;
+  std::memset(&d, 0, sizeof(d));  // padding too: the bytes key the graph cache
   d.n_theta = g.n_theta;
   d.n_phi = g.n_phi;
   d.n_a = g.n_a;
@@ -255,6 +265,7 @@ DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
   d.lds_fill = tl.lds_fill;
   d.group_tiles = tl.group_tiles;
   d.nt_store = tl.nt_store;
+  d.fill_tiles = tl.fill_tiles;
   // candidate test: enough workgroups to spread a few thousand candidates over the whole chip
   // in one pass (two candidates per wave), few enough that a near-empty event exits at once
   d.test_blocks = std::max(16, std::min(1024, (tl.n_tiles + 15) / 16));
@@ -285,7 +296,7 @@ size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct)
     b += al(16 * nn);                         // hit_slab
     b += al(16 * nn);                         // hit_pos
     b += al(16 * nn);                         // hit_rec
-    b += al(64 * nn);                         // list
+    b += al(64 * nn + 16);                    // list (+1 record of slack for the fill)
   }
   b += al(4 * (size_t)g.n_tiles);             // tile_cnt
   b += al(4 * (size_t)g.n_tiles);             // tile_off
@@ -317,7 +328,7 @@ void carve_event_scratch(const DevGrid& g, int64_t n, bool direct, char* p, EvDe
     ev->hit_slab = (int32_t*)take(16 * nn);
     ev->hit_pos = (uint32_t*)take(16 * nn);
     ev->hit_rec = (float4*)take(16 * nn);
-    ev->list = (float4*)take(64 * nn);
+    ev->list = (float4*)take(64 * nn + 16);
   }
   ev->tile_cnt = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->tile_off = (uint32_t*)take(4 * (size_t)g.n_tiles);
@@ -833,6 +844,7 @@ int ht_get_tuning(const ht_grid* grid, ht_tuning* tuning)
   tuning->group_tiles = t.group_tiles;
   tuning->cand_cap = t.cand_cap;
   tuning->nt_store = t.nt_store;
+  tuning->tiles_per_block = t.fill_tiles;
   return HT_OK;
 }
 

@@ -42,6 +42,75 @@ __device__ __forceinline__ EvDesc load_ev(const EvDesc& ev0, const EvDesc* evs)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Memory helpers. Pointers reached through descriptors are generic to the compiler, which then
+// emits FLAT instructions: those count against the LDS counter too, so every LDS wait would also
+// wait for outstanding global stores, and the compiler must assume they may alias LDS. gp()
+// states that a pointer is global memory (device memory or host memory mapped into the GPU's
+// address space). lds_barrier() synchronises the workgroup for LDS only: no workgroup here reads
+// global data written by another of its threads in the same launch, so outstanding global
+// stores need not complete before a barrier.
+// ---------------------------------------------------------------------------------------------
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gp(T* p)
+{
+  return (GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const GLOBAL T* gp(const T* p)
+{
+  return (const GLOBAL T*)p;
+}
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 ld_rec(const float4* p, size_t i)
+{
+  const f32x4 v = ((const GLOBAL f32x4*)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+// (x, r2, k) of a record: three 4-byte loads the compiler merges into one 12-byte load (the
+// unused fourth word is not loaded, so it cannot hold up a register)
+__device__ __forceinline__ void ld_xyz(const float4* p, size_t i, float* x, float* r2, float* k)
+{
+  const GLOBAL float* q = (const GLOBAL float*)p + 4 * i;
+  *x = q[0];
+  *r2 = q[1];
+  *k = q[2];
+}
+__device__ __forceinline__ void st_rec(float4* p, size_t i, float4 v)
+{
+  const f32x4 w = {v.x, v.y, v.z, v.w};
+  ((GLOBAL f32x4*)p)[i] = w;
+}
+__device__ __forceinline__ uint2 ld_cand(const uint2* p, size_t i)
+{
+  const u32x2 v = ((const GLOBAL u32x2*)p)[i];
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ void st_cand(uint2* p, size_t i, uint32_t cell, uint32_t votes)
+{
+  const u32x2 w = {cell, votes};
+  ((GLOBAL u32x2*)p)[i] = w;
+}
+// an output peak: two 4-byte stores (the caller's array need only be 4-byte aligned)
+__device__ __forceinline__ void st_peak(ht_peak* p, int64_t i, uint32_t cell, uint32_t votes)
+{
+  GLOBAL uint32_t* q = (GLOBAL uint32_t*)p + 2 * i;
+  q[0] = cell;
+  q[1] = votes;
+}
+__device__ __forceinline__ uint32_t gatomic_add(uint32_t* p, uint32_t v)
+{
+  return __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lds_barrier()
+{
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ---------------------------------------------------------------------------------------------
 // Wave / block scans (wave64)
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
@@ -70,17 +139,17 @@ __device__ uint32_t block_excl_scan(uint32_t v, uint32_t* smem, uint32_t* total)
   const int nw = blockDim.x >> 6;
   uint32_t inc = wave_incl_scan(v);
   if (lane == 63) smem[w] = inc;
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x < 64) {
     uint32_t s = threadIdx.x < (unsigned)nw ? smem[threadIdx.x] : 0u;
     uint32_t si = wave_incl_scan(s);
     if (threadIdx.x < (unsigned)nw) smem[threadIdx.x] = si - s;
     if (threadIdx.x == (unsigned)nw - 1) smem[16] = si;
   }
-  __syncthreads();
+  lds_barrier();
   uint32_t res = smem[w] + inc - v;
   *total = smem[16];
-  __syncthreads();
+  lds_barrier();
   return res;
 }
 
@@ -166,28 +235,33 @@ __global__ __launch_bounds__(kBlock) void k_prep_direct(DevGrid g, EvDesc ev0, c
   // clear all of the other array: an earlier call on a grid with more slabs may have used
   // entries past this grid's n_slabs
   if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < kCounterWords; i += kBlock) e.slab_cnt_next[i] = 0u;
+    for (int i = threadIdx.x; i < kCounterWords; i += kBlock) gp(e.slab_cnt_next)[i] = 0u;
   if ((int64_t)blockIdx.x * kBlock >= e.n_hits) return;  // uniform: whole block idle
   for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) lcnt[i] = 0u;
-  __syncthreads();
+  lds_barrier();
   const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   HitPrep p;
   p.n = 0;
   uint32_t local[4] = {0u, 0u, 0u, 0u};
   if (h < e.n_hits) {
-    p = prep_hit(g, e.x[h], e.y[h], e.z[h]);
-    for (int q = 0; q < p.n; ++q) local[q] = atomicAdd(&lcnt[p.slab[q]], 1u);
+    p = prep_hit(g, gp(e.x)[h], gp(e.y)[h], gp(e.z)[h]);
+    // constant indices keep p.slab and local in registers (a runtime index would put them in
+    // scratch memory)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < p.n) local[q] = atomicAdd(&lcnt[p.slab[q]], 1u);
   }
-  __syncthreads();
+  lds_barrier();
   for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) {
     uint32_t c = lcnt[i];
-    if (c) lcnt[i] = atomicAdd(&e.slab_cnt[i], c);
+    if (c) lcnt[i] = gatomic_add(e.slab_cnt + i, c);
   }
-  __syncthreads();
+  lds_barrier();
   if (h < e.n_hits) {
     const float4 rec = make_float4(p.x, p.r2, p.k, 0.0f);
-    for (int q = 0; q < p.n; ++q)
-      e.list[(size_t)p.slab[q] * (size_t)e.list_cap + lcnt[p.slab[q]] + local[q]] = rec;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < p.n) st_rec(e.list, (size_t)p.slab[q] * (size_t)e.list_cap + lcnt[p.slab[q]] + local[q], rec);
   }
 }
 
@@ -203,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(DevGrid g, EvDesc ev0, const Ev
     for (int i = threadIdx.x; i < kCounterWords; i += kBlock) e.slab_cnt_next[i] = 0u;
   if ((int64_t)blockIdx.x * kBlock >= e.n_hits) return;  // uniform: whole block idle
   for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) lcnt[i] = 0u;
-  __syncthreads();
+  lds_barrier();
   const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   HitPrep p;
   p.n = 0;
@@ -211,20 +285,23 @@ __global__ __launch_bounds__(kBlock) void k_prep(DevGrid g, EvDesc ev0, const Ev
   if (h < e.n_hits) {
     p = prep_hit(g, e.x[h], e.y[h], e.z[h]);
     e.hit_rec[h] = make_float4(p.x, p.r2, p.k, 0.0f);
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
       int s = q < p.n ? p.slab[q] : -1;
       e.hit_slab[4 * h + q] = s;
       if (s >= 0) local[q] = atomicAdd(&lcnt[s], 1u);
     }
   }
-  __syncthreads();
+  lds_barrier();
   for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) {
     uint32_t c = lcnt[i];
     if (c) lcnt[i] = atomicAdd(&e.slab_cnt[i], c);
   }
-  __syncthreads();
+  lds_barrier();
   if (h < e.n_hits)
-    for (int q = 0; q < p.n; ++q) e.hit_pos[4 * h + q] = lcnt[p.slab[q]] + local[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < p.n) e.hit_pos[4 * h + q] = lcnt[p.slab[q]] + local[q];
 }
 
 // Every workgroup scans the slab counts into LDS (they are few); workgroup 0 also publishes the
@@ -250,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket(DevGrid g, EvDesc ev0, const 
     run += c;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) e.slab_off[ns] = total;
-  __syncthreads();
+  lds_barrier();
   const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (h >= e.n_hits) return;
   const float4 rec = e.hit_rec[h];
@@ -265,24 +342,25 @@ __global__ __launch_bounds__(kBlock) void k_bucket(DevGrid g, EvDesc ev0, const 
 // Candidates (cells >= threshold) of one tile, from the tile's counts in LDS: the tile reserves
 // a chunk of the event's candidate pool with one atomic, then each wave writes the candidates
 // of its quarter of the tile in cell order (ballot compaction), so every tile's chunk is sorted
-// by cell index. A tile whose candidates do not fit the pool is marked overflowed.
+// by cell index, and clears them in LDS. A tile whose candidates do not fit the pool is marked
+// overflowed.
 // Called by the whole block; `any` is nonzero iff the tile holds a candidate (a block-uniform
 // hint from the flush; the reservation uses this function's own count); s_small: >= 9 words.
 // ---------------------------------------------------------------------------------------------
 __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uint32_t cell0,
-                                const uint32_t* s_tile, uint32_t L, uint32_t any, uint32_t* s_small)
+                                uint32_t* s_tile, uint32_t L, uint32_t any, uint32_t* s_small)
 {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t T = g.threshold;
   if (threadIdx.x == 0) {
     // peak counts start at zero; the candidate test (a later launch) adds to them
-    e.tile_pk[tile] = 0u;
-    if (tile % g.group_tiles == 0) e.group_pk[tile / g.group_tiles] = 0u;
+    gp(e.tile_pk)[tile] = 0u;
+    if (tile % g.group_tiles == 0) gp(e.group_pk)[tile / g.group_tiles] = 0u;
   }
   if (any == 0) {
     if (threadIdx.x == 0) {
-      e.tile_cnt[tile] = 0u;
-      e.tile_off[tile] = 0u;
+      gp(e.tile_cnt)[tile] = 0u;
+      gp(e.tile_off)[tile] = 0u;
     }
     return;
   }
@@ -295,7 +373,7 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
     cnt += (uint32_t)__popcll(__ballot(c));
   }
   if (lane == 0) s_small[wave] = cnt;
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) {
     const uint32_t w0 = s_small[0], w1 = s_small[1], w2 = s_small[2];
     const uint32_t total = w0 + w1 + w2 + s_small[3];
@@ -303,111 +381,149 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
     s_small[5] = w0;
     s_small[6] = w0 + w1;
     s_small[7] = w0 + w1 + w2;
-    uint32_t base = atomicAdd(&e.slab_cnt[kPoolCounter], total);
+    uint32_t base = gatomic_add(e.slab_cnt + kPoolCounter, total);
     if (base > e.pool_cap || total > e.pool_cap - base) {
       // reservations are contiguous, so at most one starts inside the pool and crosses its
       // end: it marks where the written entries stop
-      if (base <= e.pool_cap) e.slab_cnt[kPoolCut] = e.pool_cap - base + 1u;
-      e.ovf_list[atomicAdd(&e.slab_cnt[kOvfCounter], 1u)] = (uint32_t)tile;
+      if (base <= e.pool_cap) gp(e.slab_cnt)[kPoolCut] = e.pool_cap - base + 1u;
+      gp(e.ovf_list)[gatomic_add(e.slab_cnt + kOvfCounter, 1u)] = (uint32_t)tile;
       base = kTileOverflow;
     }
     s_small[8] = base;
-    e.tile_cnt[tile] = total;
-    e.tile_off[tile] = base;
+    gp(e.tile_cnt)[tile] = total;
+    gp(e.tile_off)[tile] = base;
   }
-  __syncthreads();
+  lds_barrier();
   const uint32_t base = s_small[8];
-  if (base == kTileOverflow) return;
+  const bool keep = base != kTileOverflow;
   uint32_t run = base + s_small[4 + wave];
   for (uint32_t b = s0; b < s1; b += 64) {
     const uint32_t i = b + lane;
     const uint32_t v = i < s1 ? s_tile[i] : 0u;
     const bool c = i < s1 && v >= T;
     const uint64_t m = __ballot(c);
-    if (c) e.pool[run + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = make_uint2(cell0 + i, v);
+    if (c) {
+      if (keep) st_cand(e.pool, run + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)), cell0 + i, v);
+      s_tile[i] = 0u;  // leaves the LDS tile clear for a workgroup that fills another tile
+    }
     run += (uint32_t)__popcll(m);
   }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Fill through an LDS tile of ROWS x n_b counters.
+// Fill through an LDS tile of ROWS x n_b counters. The grid holds ceil(n_tiles / fill_tiles)
+// workgroups; workgroup w fills tiles w, w + G, w + 2G, ... (G workgroups), so at any moment the
+// workgroups write one contiguous stretch of the matrix. Per tile: the slab's record list is
+// read (with direct lists the first kListCache records per thread are loaded together with the
+// list length, in one memory round trip; longer lists stream the rest), the votes go to LDS,
+// the tile is written out once, its candidates are pooled, and the LDS tile is left all zero.
 // ---------------------------------------------------------------------------------------------
+constexpr int kListCache = 2;
+
 template <int ROWS, bool VEC, bool EMIT, bool NT>
 __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   extern __shared__ uint32_t smem[];
   EvDesc e = load_ev(ev0, evs);
-  const int tile = blockIdx.x;
-  const int slab = tile / g.tiles_per_slab;
-  const int a0 = (tile - slab * g.tiles_per_slab) * ROWS;
-  const int rows = min(ROWS, g.n_a - a0);
   const uint32_t nb = (uint32_t)g.n_b;
-  const uint32_t L = (uint32_t)rows * nb;
   const uint32_t Lpad = ((uint32_t)ROWS * nb + 3u) & ~3u;
   uint32_t* s_tile = smem;
   uint32_t* s_small = smem + Lpad;  // 16 words
-
   u32x4* s4 = reinterpret_cast<u32x4*>(s_tile);
   const u32x4 zero4 = {0u, 0u, 0u, 0u};
   for (uint32_t i = threadIdx.x; i < Lpad / 4; i += kBlock) s4[i] = zero4;
-  if (EMIT && threadIdx.x == 0) s_small[12] = 0u;
-  __syncthreads();
 
-  size_t beg, end;
-  if (e.list_cap > 0) {
-    beg = (size_t)slab * (size_t)e.list_cap;
-    end = beg + e.slab_cnt[slab];
-  } else {
-    beg = e.slab_off[slab];
-    end = e.slab_off[slab + 1];
-  }
-  float a2r[ROWS];
-#pragma unroll
-  for (int r = 0; r < ROWS; ++r) a2r[r] = g.a2[min(a0 + r, g.n_a - 1)];
   const float b_min = g.b_min, inv_db = g.inv_db, nb_f = g.nb_f;
-  for (size_t h = beg + threadIdx.x; h < end; h += kBlock) {
-    const float4 rec = e.list[h];
-    const float x = rec.x, r2 = rec.y, k = rec.z;
+  const uint32_t T = g.threshold;
+  for (int tile = blockIdx.x; tile < g.n_tiles; tile += (int)gridDim.x) {  // uniform
+    const int slab = tile / g.tiles_per_slab;
+    const int a0 = (tile - slab * g.tiles_per_slab) * ROWS;
+    const int rows = min(ROWS, g.n_a - a0);
+    const uint32_t L = (uint32_t)rows * nb;
+    size_t beg;
+    uint32_t n, last;  // records in the list; last readable record (before n is known)
+    if (e.list_cap > 0) {
+      beg = (size_t)slab * (size_t)e.list_cap;
+      n = gp(e.slab_cnt)[slab];
+      last = (uint32_t)e.list_cap - 1u;
+    } else {
+      // the packed list has one record of slack past its end, so beg is always readable
+      const uint32_t o = gp(e.slab_off)[slab];
+      beg = o;
+      n = gp(e.slab_off)[slab + 1] - o;
+      last = n > 0 ? n - 1u : 0u;
+    }
+    // unconditional loads from clamped indices: no branch, so the values land straight in the
+    // registers the votes read, and the loads overlap the list-length load
+    float cx[kListCache], cr2[kListCache], ck[kListCache];
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      if (r < rows) {
-        float ax = a2r[r] * x;
-        float num = r2 - ax;
-        float B = num * k;
-        float d = B - b_min;
-        float f = d * inv_db;
-        if (f >= 0.0f && f < nb_f) atomicAdd(&s_tile[(uint32_t)r * nb + (uint32_t)(int)f], 1u);
+    for (int c = 0; c < kListCache; ++c)
+      ld_xyz(e.list, beg + min(threadIdx.x + (uint32_t)c * kBlock, last), &cx[c], &cr2[c], &ck[c]);
+    float a2r[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) a2r[r] = g.a2[min(a0 + r, g.n_a - 1)];
+    if (EMIT && threadIdx.x == 0) s_small[12] = 0u;
+    // the LDS tile is zero: set at the start, restored at the end of every tile
+    lds_barrier();
+    auto vote = [&](float x, float r2, float k) {
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) {
+        if (r < rows) {
+          float ax = a2r[r] * x;
+          float num = r2 - ax;
+          float B = num * k;
+          float d = B - b_min;
+          float f = d * inv_db;
+          if (f >= 0.0f && f < nb_f) atomicAdd(&s_tile[(uint32_t)r * nb + (uint32_t)(int)f], 1u);
+        }
+      }
+    };
+#pragma unroll
+    for (int c = 0; c < kListCache; ++c)
+      if (threadIdx.x + (uint32_t)c * kBlock < n) vote(cx[c], cr2[c], ck[c]);
+    for (uint32_t h = kListCache * kBlock + threadIdx.x; h < n; h += kBlock) {
+      float x, r2, k;
+      ld_xyz(e.list, beg + h, &x, &r2, &k);
+      vote(x, r2, k);
+    }
+    lds_barrier();
+
+    // write the tile out once; without candidates to pool, clear LDS on the way
+    const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
+    GLOBAL uint32_t* dst = gp(e.acc) + cell0;
+    uint32_t ncand = 0;
+    if (VEC) {
+      GLOBAL u32x4* d4 = reinterpret_cast<GLOBAL u32x4*>(dst);
+      for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) {
+        const u32x4 v = s4[i];
+        if (NT) __builtin_nontemporal_store(v, d4 + i);
+        else d4[i] = v;
+        if (EMIT) {
+          // keep only the candidates; emission clears those
+          const u32x4 kept = {v.x >= T ? v.x : 0u, v.y >= T ? v.y : 0u, v.z >= T ? v.z : 0u,
+                              v.w >= T ? v.w : 0u};
+          ncand += (v.x >= T ? 1u : 0u) + (v.y >= T ? 1u : 0u) + (v.z >= T ? 1u : 0u) + (v.w >= T ? 1u : 0u);
+          s4[i] = kept;
+        } else {
+          s4[i] = zero4;
+        }
+      }
+    } else {
+      for (uint32_t i = threadIdx.x; i < L; i += kBlock) {
+        const uint32_t v = s_tile[i];
+        if (NT) __builtin_nontemporal_store(v, dst + i);
+        else dst[i] = v;
+        if (EMIT) ncand += v >= T ? 1u : 0u;
+        s_tile[i] = (EMIT && v >= T) ? v : 0u;
       }
     }
-  }
-  __syncthreads();
-
-  const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
-  uint32_t* dst = e.acc + cell0;
-  const uint32_t T = g.threshold;
-  uint32_t ncand = 0;
-  if (VEC) {
-    u32x4* d4 = reinterpret_cast<u32x4*>(dst);
-    for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) {
-      u32x4 v = s4[i];
-      if (NT) __builtin_nontemporal_store(v, d4 + i);
-      else d4[i] = v;
-      if (EMIT)
-        ncand += (v.x >= T ? 1u : 0u) + (v.y >= T ? 1u : 0u) + (v.z >= T ? 1u : 0u) + (v.w >= T ? 1u : 0u);
+    if (EMIT) {
+      ncand = wave_sum(ncand);
+      if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_small[12], ncand);
+      lds_barrier();
+      emit_candidates(g, e, tile, cell0, s_tile, L, s_small[12], s_small);
     }
-  } else {
-    for (uint32_t i = threadIdx.x; i < L; i += kBlock) {
-      uint32_t v = s_tile[i];
-      if (NT) __builtin_nontemporal_store(v, dst + i);
-      else dst[i] = v;
-      if (EMIT) ncand += v >= T ? 1u : 0u;
-    }
-  }
-  if (EMIT) {
-    ncand = wave_sum(ncand);
-    if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_small[12], ncand);
-    __syncthreads();
-    emit_candidates(g, e, tile, cell0, s_tile, L, s_small[12], s_small);
+    // the LDS tile is all zero again; the next tile's votes start after its first barrier
   }
 }
 
@@ -420,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_scan(DevGrid g, EvDesc ev0, con
   EvDesc e = load_ev(ev0, evs);
   const int tile = blockIdx.x;
   if (tile == 0)
-    for (int i = threadIdx.x; i < kCounterWords; i += kBlock) e.slab_cnt_next[i] = 0u;
+    for (int i = threadIdx.x; i < kCounterWords; i += kBlock) gp(e.slab_cnt_next)[i] = 0u;
   const int slab = tile / g.tiles_per_slab;
   const int a0 = (tile - slab * g.tiles_per_slab) * g.rows;
   const int rows = min(g.rows, g.n_a - a0);
@@ -430,13 +546,13 @@ __global__ __launch_bounds__(kBlock) void k_cand_scan(DevGrid g, EvDesc ev0, con
   uint32_t* s_tile = smem;
   uint32_t* s_small = smem + Lpad;
   if (threadIdx.x == 0) s_small[12] = 0u;
-  __syncthreads();
+  lds_barrier();
   const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
-  const uint32_t* src = e.acc + cell0;
+  const GLOBAL uint32_t* src = gp(e.acc) + cell0;
   const uint32_t T = g.threshold;
   uint32_t ncand = 0;
   if (VEC) {
-    const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+    const GLOBAL u32x4* s4 = reinterpret_cast<const GLOBAL u32x4*>(src);
     u32x4* l4 = reinterpret_cast<u32x4*>(s_tile);
     for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) {
       const u32x4 v = __builtin_nontemporal_load(s4 + i);
@@ -452,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_scan(DevGrid g, EvDesc ev0, con
   }
   ncand = wave_sum(ncand);
   if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_small[12], ncand);
-  __syncthreads();
+  lds_barrier();
   emit_candidates(g, e, tile, cell0, s_tile, L, s_small[12], s_small);
 }
 
@@ -499,14 +615,14 @@ __device__ bool is_peak(const DevGrid& g, const uint32_t* __restrict__ acc, uint
         const int bb = (int)b + db;
         if (bb < 0 || bb >= (int)nb || (dt == 0 && dp == 0 && da == 0 && db == 0)) continue;
         const uint32_t n = rowc + (uint32_t)bb;
-        const uint32_t w = acc[n];
+        const uint32_t w = gp(acc)[n];
         beaten |= w > v || (w == v && n < c);
       }
     }
     return !beaten;
   }
   const uint32_t w0 = min(max(b, 1u) - 1u, nb - 3u);
-  U32x3 row[27];
+  uint32_t row[27][3];
   uint32_t base[27];
   bool rv[27];
 #pragma unroll
@@ -516,13 +632,16 @@ __device__ bool is_peak(const DevGrid& g, const uint32_t* __restrict__ acc, uint
     rv[k] = tt >= 0 && tt < g.n_theta && aa >= 0 && aa < (int)na;
     const uint32_t pp = dp < 0 ? pm : (dp > 0 ? pp1 : p);
     base[k] = (rv[k] ? (((uint32_t)tt * np + pp) * na + (uint32_t)aa) * nb : c - b) + w0;
-    row[k] = *reinterpret_cast<const U32x3*>(acc + base[k]);
+    const GLOBAL uint32_t* rw = gp(acc) + base[k];
+    row[k][0] = rw[0];
+    row[k][1] = rw[1];
+    row[k][2] = rw[2];
   }
   bool beaten = false;
 #pragma unroll
   for (int k = 0; k < 27; ++k) {
     const bool centre_row = k == 13;
-    const uint32_t vals[3] = {row[k].v0, row[k].v1, row[k].v2};
+    const uint32_t* vals = row[k];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const uint32_t bb = w0 + (uint32_t)q;
@@ -553,8 +672,8 @@ __device__ void group_prefix(const EvDesc& e, int t0, int nt, uint32_t* s_pre, u
   // tiles nt..kGroupTiles-1 count zero, so s_pre[nt..kGroupTiles] all equal the group total
   if (threadIdx.x < kGroupTiles) {
     const int i = threadIdx.x;
-    uint32_t c = i < nt ? counts[t0 + i] : 0u;
-    const uint32_t off = i < nt ? e.tile_off[t0 + i] : 0u;
+    uint32_t c = i < nt ? gp(counts)[t0 + i] : 0u;
+    const uint32_t off = i < nt ? gp(e.tile_off)[t0 + i] : 0u;
     const uint32_t ovf = off == kTileOverflow ? 1u : 0u;
     s_ovf[i] = ovf;
     s_off[i] = off;
@@ -597,14 +716,14 @@ __device__ bool row_beats(const DevGrid& g, const uint32_t* __restrict__ acc, ui
     for (uint32_t bb = b == 0 ? 0 : b - 1; bb <= b + 1 && bb < nb; ++bb) {
       if (centre_row && bb == b) continue;
       const uint32_t n = rowc + bb;
-      const uint32_t w = acc[n];
+      const uint32_t w = gp(acc)[n];
       beaten |= w > v || (w == v && n < c);
     }
     return beaten;
   }
   const uint32_t w0 = min(max(b, 1u) - 1u, nb - 3u);
-  const U32x3 row = *reinterpret_cast<const U32x3*>(acc + rowc + w0);
-  const uint32_t vals[3] = {row.v0, row.v1, row.v2};
+  const GLOBAL uint32_t* rw = gp(acc) + rowc + w0;
+  const uint32_t vals[3] = {rw[0], rw[1], rw[2]};
   bool beaten = false;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -623,8 +742,8 @@ __device__ __forceinline__ void count_peak(const DevGrid& g, const EvDesc& e, ui
   const uint32_t slab = c / slab_cells;
   const uint32_t a = (c - slab * slab_cells) / nb;
   const uint32_t tile = slab * (uint32_t)g.tiles_per_slab + a / (uint32_t)g.rows;
-  atomicAdd(&e.tile_pk[tile], 1u);
-  atomicAdd(&e.group_pk[tile / (uint32_t)g.group_tiles], 1u);
+  gatomic_add(e.tile_pk + tile, 1u);
+  gatomic_add(e.group_pk + tile / (uint32_t)g.group_tiles, 1u);
 }
 
 // Peak test of every pooled candidate, spread evenly over the grid whatever tiles they came
@@ -637,8 +756,8 @@ __device__ __forceinline__ void count_peak(const DevGrid& g, const EvDesc& e, ui
 __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   EvDesc e = load_ev(ev0, evs);
-  const uint32_t cut = e.slab_cnt[kPoolCut];
-  const uint32_t n_valid = min(cut ? e.pool_cap + 1u - cut : e.slab_cnt[kPoolCounter], e.pool_cap);
+  const uint32_t cut = gp(e.slab_cnt)[kPoolCut];
+  const uint32_t n_valid = min(cut ? e.pool_cap + 1u - cut : gp(e.slab_cnt)[kPoolCounter], e.pool_cap);
   const int lane = threadIdx.x & 63, half = lane >> 5, k = lane & 31;
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const uint32_t n_waves = gridDim.x * (kBlock / 64);
@@ -650,41 +769,41 @@ __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, con
       uint2 cv = make_uint2(0u, 0u);
       bool beaten = false;
       if (live) {
-        cv = e.pool[i];
+        cv = ld_cand(e.pool, i);
         if (k < 27) beaten = row_beats(g, acc, cv.x, cv.y, k);
       }
       const uint64_t m = __ballot(beaten);
       const uint32_t hm = (uint32_t)(m >> (32 * half));
       if (live && k == 0) {
         const bool pk = hm == 0u;
-        e.pk_flag[i] = pk ? 1 : 0;
+        gp(e.pk_flag)[i] = pk ? 1 : 0;
         if (pk) count_peak(g, e, cv.x);
       }
     }
   } else {
     const uint32_t n_threads = gridDim.x * kBlock;
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n_valid; i += n_threads) {
-      const uint2 cv = e.pool[i];
+      const uint2 cv = ld_cand(e.pool, i);
       const bool pk = is_peak(g, acc, cv.x, cv.y);
-      e.pk_flag[i] = pk ? 1 : 0;
+      gp(e.pk_flag)[i] = pk ? 1 : 0;
       if (pk) count_peak(g, e, cv.x);
     }
   }
-  const uint32_t n_ovf = e.slab_cnt[kOvfCounter];
+  const uint32_t n_ovf = gp(e.slab_cnt)[kOvfCounter];
   for (uint32_t j = wave; j < n_ovf; j += n_waves) {
-    const int tile = (int)e.ovf_list[j];
+    const int tile = (int)gp(e.ovf_list)[j];
     uint32_t cell0, L;
     tile_range(g, tile, &cell0, &L);
     uint32_t mine = 0;
     for (uint32_t q = (uint32_t)lane; q < L; q += 64) {
       const uint32_t c = cell0 + q;
-      const uint32_t v = acc[c];
+      const uint32_t v = gp(acc)[c];
       if (v >= g.threshold && is_peak(g, acc, c, v)) ++mine;
     }
     mine = wave_sum(mine);
     if (lane == 0 && mine) {
-      atomicAdd(&e.tile_pk[tile], mine);
-      atomicAdd(&e.group_pk[tile / g.group_tiles], mine);
+      gatomic_add(e.tile_pk + tile, mine);
+      gatomic_add(e.group_pk + tile / g.group_tiles, mine);
     }
   }
 }
@@ -706,21 +825,21 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
   const int t0 = G * g.group_tiles;
   const int nt = min(g.group_tiles, g.n_tiles - t0);
   uint32_t part = 0;
-  for (int i = threadIdx.x; i < G; i += kBlock) part += e.group_pk[i];
+  for (int i = threadIdx.x; i < G; i += kBlock) part += gp(e.group_pk)[i];
   const uint32_t base32 = block_sum(part, smem);
   const int64_t base = (int64_t)base32;
-  if (G == (int)gridDim.x - 1 && threadIdx.x == 0) *e.n_found = base + e.group_pk[G];
+  if (G == (int)gridDim.x - 1 && threadIdx.x == 0) *gp(e.n_found) = base + gp(e.group_pk)[G];
   if (base >= e.cap) return;  // uniform
   group_prefix(e, t0, nt, s_pre, s_ovf, s_off, e.tile_cnt);
   if (threadIdx.x >= 64 && threadIdx.x < 64 + kGroupTiles) {
     // second wave: prefix of the peak counts of all the group's tiles
     const int i = threadIdx.x - 64;
-    const uint32_t c = i < nt ? e.tile_pk[t0 + i] : 0u;
+    const uint32_t c = i < nt ? gp(e.tile_pk)[t0 + i] : 0u;
     const uint32_t inc = wave_incl_scan(c);
     s_out[i + 1] = inc;
     if (i == 0) s_out[0] = 0u;
   }
-  __syncthreads();
+  lds_barrier();
   const uint32_t total = s_pre[kGroupTiles];
   uint32_t run = 0;
   for (uint32_t b0 = 0; b0 < total; b0 += kBlock) {
@@ -731,21 +850,18 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
     if (f < total) {
       tl = group_tile_of(s_pre, f);
       idx = (size_t)s_off[tl] + (f - s_pre[tl]);
-      pk = e.pk_flag[idx] != 0;
+      pk = gp(e.pk_flag)[idx] != 0;
     }
     uint32_t tot;
     const uint32_t pos = run + block_excl_scan(pk ? 1u : 0u, smem, &tot);
     // the first candidate of a tile records how many of the group's pooled peaks precede it
     if (f < total && f == s_pre[tl]) s_first[tl] = pos;
-    __syncthreads();
+    lds_barrier();
     if (pk) {
       const int64_t o = base + s_out[tl] + (pos - s_first[tl]);
       if (o < e.cap) {
-        const uint2 cv = e.pool[idx];
-        ht_peak q;
-        q.cell = cv.x;
-        q.votes = cv.y;
-        e.out[o] = q;
+        const uint2 cv = ld_cand(e.pool, idx);
+        st_peak(e.out, o, cv.x, cv.y);
       }
     }
     run += tot;
@@ -763,17 +879,12 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
       uint32_t c = 0, v = 0;
       if (i < L) {
         c = cell0 + i;
-        v = acc[c];
+        v = gp(acc)[c];
         pk = v >= g.threshold && is_peak(g, acc, c, v);
       }
       const uint64_t m = __ballot(pk);
       const int64_t o = base + s_out[tl] + r + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-      if (pk && o < e.cap) {
-        ht_peak q;
-        q.cell = c;
-        q.votes = v;
-        e.out[o] = q;
-      }
+      if (pk && o < e.cap) st_peak(e.out, o, c, v);
       r += (uint32_t)__popcll(m);
     }
   }
@@ -871,7 +982,7 @@ template <int ROWS, bool NT>
 hipError_t launch_fill_rows(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                             bool vec, bool emit, size_t lds, hipStream_t s)
 {
-  dim3 grid(g.n_tiles, n_ev);
+  dim3 grid((g.n_tiles + g.fill_tiles - 1) / g.fill_tiles, n_ev);  // interleaved tiles
   if (vec) {
     if (emit) hipLaunchKernelGGL((k_fill<ROWS, true, true, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
     else hipLaunchKernelGGL((k_fill<ROWS, true, false, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
@@ -924,9 +1035,10 @@ hipError_t launch_prep(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, i
 hipError_t launch_fill(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                        bool emit, hipStream_t s)
 {
-  const bool vec = (g.n_b % 4) == 0;
+  // store kind 2: 4-byte stores (the dword path), otherwise 16-byte stores where rows allow
+  const bool vec = (g.n_b % 4) == 0 && g.nt_store != 2;
   const size_t lds = fill_lds_bytes(g);
-  if (g.nt_store) return launch_fill_nt<true>(g, ev0, evs, n_ev, vec, emit, lds, s);
+  if (g.nt_store == 1) return launch_fill_nt<true>(g, ev0, evs, n_ev, vec, emit, lds, s);
   return launch_fill_nt<false>(g, ev0, evs, n_ev, vec, emit, lds, s);
 }
 

@@ -1,7 +1,8 @@
 """Autotuner for the launch shape of the fill and peak kernels (ht_set_tuning).
 
-For one grid and a few representative events it times every candidate shape (A rows per fill
-tile, tiles per peak workgroup, store kind of the matrix flush), keeps only candidates whose vote
+For one grid and a few representative events it times candidate shapes (A rows per fill tile,
+fill tiles per workgroup, store kind of the matrix write, tiles per peak workgroup), keeps only
+candidates whose vote
 matrices and peak lists are bit-identical to those of the default shape, and applies the
 fastest. Results are cached in a JSON file keyed by GPU architecture and grid.
 """
@@ -31,11 +32,13 @@ def grid_key(spec) -> str:
 
 
 def candidates(spec):
+    """Fill shapes (A rows per tile, tiles per workgroup, store kind) first, each with the
+    default peak-group size; then the peak-group sizes are tried on the fastest fill shape."""
     g = B.make_grid(spec)
     rows = [r for r in (1, 2, 4, 8, 16, 32, 64) if r * g.n_b * 4 <= 57344 and r <= max(1, g.n_a)]
     rows = rows[-3:] if len(rows) > 3 else rows
-    for r, gt, nt in itertools.product(rows, (16, 32, 64), (0, 1)):
-        yield B.Tuning(r, gt, 0, nt)
+    for r, tpb, nt in itertools.product(rows, (1, 4), (0, 1, 2)):
+        yield B.Tuning(r, 0, 0, nt, tpb)
 
 
 def _run(spec, hits, acc, out, nf, cap, reps):
@@ -66,11 +69,12 @@ def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool 
         ref.append((acc.clone(), B.peaks_to_host(out, nf, capacity)))
     t_default = _run(spec, hits, acc, out, nf, capacity, reps)
     results = []
-    for cand in candidates(spec):
+
+    def trial(cand):
         try:
             B.ht_set_tuning(spec, cand)
         except B.HTError:
-            continue
+            return None
         cand = B.ht_get_tuning(spec)  # the effective shape, defaults filled in
         exact = True
         for (x, y, z), (racc, rpk) in zip(hits, ref):
@@ -82,8 +86,19 @@ def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool 
                 exact = False
                 break
         t = _run(spec, hits, acc, out, nf, capacity, reps) if exact else None
-        results.append({"tuning": cand.as_dict(), "us_per_event": None if t is None else t * 1e6,
-                        "bit_exact": exact})
+        r = {"tuning": cand.as_dict(), "us_per_event": None if t is None else t * 1e6,
+             "bit_exact": exact}
+        results.append(r)
+        return r
+
+    for cand in candidates(spec):
+        trial(cand)
+    ok = [r for r in results if r["bit_exact"]]
+    if ok:
+        f = min(ok, key=lambda r: r["us_per_event"])["tuning"]
+        for gt in (16, 32, 64):
+            if gt != f["group_tiles"]:
+                trial(B.Tuning(f["rows"], gt, 0, f["nt_store"], f["tiles_per_block"]))
     B.ht_set_tuning(spec)
     ok = [r for r in results if r["bit_exact"]]
     best = min(ok, key=lambda r: r["us_per_event"]) if ok else None

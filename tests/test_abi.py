@@ -126,14 +126,17 @@ def test_tuning_validated_and_applied_on_host(lib):
     default = B.ht_get_tuning(spec).as_dict()
     assert default["rows"] == B.ht_tiling(spec)["rows"]
     for bad in [dict(rows=3), dict(rows=128), dict(rows=32),  # 32 x 1024 x 4 B exceeds the LDS tile
-                dict(group_tiles=8), dict(cand_cap=3), dict(cand_cap=8192), dict(nt_store=2)]:
+                dict(group_tiles=8), dict(cand_cap=3), dict(cand_cap=8192), dict(nt_store=3),
+                dict(tiles_per_block=3), dict(tiles_per_block=128), dict(tiles_per_block=-1)]:
         with pytest.raises(B.HTError):
             B.ht_set_tuning(spec, **bad)
         assert B.ht_get_tuning(spec).as_dict() == default
-    B.ht_set_tuning(spec, rows=4, group_tiles=32, cand_cap=128, nt_store=1)
+    assert default["tiles_per_block"] >= 1 and default["nt_store"] in (0, 1, 2)
+    B.ht_set_tuning(spec, rows=4, group_tiles=32, cand_cap=128, nt_store=2, tiles_per_block=16)
     try:
         got = B.ht_get_tuning(spec).as_dict()
-        assert got == {"rows": 4, "group_tiles": 32, "cand_cap": 128, "nt_store": 1}
+        assert got == {"rows": 4, "group_tiles": 32, "cand_cap": 128, "nt_store": 2,
+                       "tiles_per_block": 16}
         # the threshold is not part of the key
         other = synth.GridSpec(4, 16, 1024, 1024, threshold=3)
         assert B.ht_get_tuning(other).as_dict() == got

@@ -196,9 +196,11 @@ def test_every_tile_shape_bit_exact(gpu, rows):
     for spec, ev in ((CFG0, synth.make_event(0, 3)), (synth.GridSpec(4, 16, 100, 40, threshold=4),
                                                        synth.make_event(0, 4))):
         M, votes, oc, ov, on = oracle_run(spec, ev.x, ev.y, ev.z)
-        for gt, nt in ((16, 0), (64, 1)):
-            say("tile rows", rows, "group tiles", gt, "nt", nt, "grid", spec.shape)
-            B.ht_set_tuning(spec, rows=rows, group_tiles=gt, nt_store=nt)
+        # tiles per workgroup 3 is not allowed; 1, 4 and 16 cover workgroups whose tiles
+        # stay in one slab, span slabs, and run past the last tile
+        for gt, nt, tpb in ((16, 0, 1), (64, 1, 4), (32, 2, 16)):
+            say("tile rows", rows, "group tiles", gt, "store", nt, "tiles/block", tpb, "grid", spec.shape)
+            B.ht_set_tuning(spec, rows=rows, group_tiles=gt, nt_store=nt, tiles_per_block=tpb)
             try:
                 gM, gc, gv, gn = gpu_fused(B, spec, ev.x, ev.y, ev.z)
             finally:
@@ -211,14 +213,14 @@ def test_paper_grid_tile_shapes_bit_exact(gpu):
     ev = synth.make_event(1, 7)
     M, votes, oc, ov, on = oracle_run(CFG1, ev.x, ev.y, ev.z)
     for rows in (1, 2, 4, 8):
-        for nt in (0, 1):
-            say("workload 1, rows", rows, "nt", nt)
-            B.ht_set_tuning(CFG1, rows=rows, nt_store=nt, group_tiles=32)
+        for nt, tpb in ((0, 1), (1, 8), (2, 16), (0, 64)):
+            say("workload 1, rows", rows, "store", nt, "tiles/block", tpb)
+            B.ht_set_tuning(CFG1, rows=rows, nt_store=nt, group_tiles=32, tiles_per_block=tpb)
             try:
                 gM, gc, gv, gn = gpu_fused(B, CFG1, ev.x, ev.y, ev.z)
             finally:
                 B.ht_set_tuning(CFG1)
-            assert_same(CFG1, gM, gc, gv, gn, M, oc, ov, on, "rows %d nt %d" % (rows, nt))
+            assert_same(CFG1, gM, gc, gv, gn, M, oc, ov, on, "rows %d store %d tpb %d" % (rows, nt, tpb))
 
 
 def test_candidate_overflow_uses_dense_path(gpu):
