@@ -69,13 +69,21 @@ typedef enum ht_status {
   HT_EDEVICE = -5     /* a HIP runtime call failed */
 } ht_status;
 
-/* Binning of the vote matrix. Limits: n_theta >= 1, n_phi >= 3, n_theta*n_phi <= 4096,
- * 1 <= n_a, n_b <= 2^24, n_theta*n_phi*n_a*n_b <= 2^32, finite ranges with min < max,
- * threshold >= 1. A and B are in the units of the hit coordinates (mm); ranges are half-open. */
+/* Binning of the vote matrix. Limits: n_theta >= 1, n_phi >= 3 (>= 1 with phi_sectors),
+ * n_theta*n_phi <= 4096, 1 <= n_a, n_b <= 2^24, n_theta*n_phi*n_a*n_b <= 2^32, finite ranges
+ * with min < max, threshold >= 1, phi_sectors 0 or 1. A and B are in the units of the hit
+ * coordinates (mm); ranges are half-open.
+ * phi_sectors = 0: the 4-D transform of section 2: phi cells widened by half a bin (two per
+ *   hit), phi periodic in the peak search.
+ * phi_sectors = 1: the sector variant of section 4: the n_phi phi cells are sectors of the
+ *   transverse plane transformed independently, one M_H(A, B, theta) each: a hit votes in its
+ *   own sector only, and a peak is compared with its (theta, A, B) neighbours in that sector
+ *   only (3^3 box); the peak list is the merge of all sectors' peaks by ascending cell. */
 typedef struct ht_grid {
   int32_t n_theta, n_phi, n_a, n_b;
   float a_min, a_max, b_min, b_max;
   uint32_t threshold;
+  int32_t phi_sectors;
 } ht_grid;
 
 /* One local maximum: its cell index and vote count. */

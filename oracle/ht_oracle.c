@@ -51,8 +51,16 @@
  *      (theta, A and B are not periodic, so neighbours outside the range are absent; phi wraps
  *      around), M[c] > M[n] or (M[c] == M[n] and c < n).  Peaks are listed by ascending c.
  *
- * Grid limits: n_theta >= 1, n_phi >= 3, 1 <= n_a, n_b <= 2^24, n_theta*n_phi*n_a*n_b <= 2^32,
- * finite ranges with min < max, threshold >= 1.
+ * Sector variant (paper section 4, phi_sectors = 1): the transverse plane is split into n_phi
+ * sectors that are read out and transformed independently, one M_H(A, B, theta) per sector, and
+ * the results are merged. Each phi cell is then a sector:
+ *   O3' a hit belongs to the one sector holding its azimuth, s_phi>>1 (no widening in phi);
+ *       theta cells are as in O3;
+ *   O6' the neighbourhood is the 3^3 box in (theta, A, B) inside the peak's own sector (no phi
+ *       neighbours); the merged list is every sector's peaks by ascending c.
+ *
+ * Grid limits: n_theta >= 1, n_phi >= 3 (>= 1 with phi_sectors), 1 <= n_a, n_b <= 2^24,
+ * n_theta*n_phi*n_a*n_b <= 2^32, finite ranges with min < max, threshold >= 1, phi_sectors 0 or 1.
  */
 #include <math.h>
 #include <stdint.h>
@@ -66,6 +74,7 @@ typedef struct oracle_grid {
   int32_t n_theta, n_phi, n_a, n_b;
   float a_min, a_max, b_min, b_max;
   uint32_t threshold;
+  int32_t phi_sectors; /* 0: widened, periodic phi cells; 1: independent phi sectors */
 } oracle_grid;
 
 static const double kPi = 3.14159265358979323846;
@@ -73,7 +82,9 @@ static const double kPi = 3.14159265358979323846;
 int oracle_check_grid(const oracle_grid* g)
 {
   if (!g) return ORACLE_EINVAL;
-  if (g->n_theta < 1 || g->n_phi < 3 || g->n_a < 1 || g->n_b < 1) return ORACLE_EINVAL;
+  if (g->phi_sectors != 0 && g->phi_sectors != 1) return ORACLE_EINVAL;
+  if (g->n_theta < 1 || g->n_phi < (g->phi_sectors ? 1 : 3) || g->n_a < 1 || g->n_b < 1)
+    return ORACLE_EINVAL;
   if (g->n_a > (1 << 24) || g->n_b > (1 << 24)) return ORACLE_EINVAL;
   if (!isfinite(g->a_min) || !isfinite(g->a_max) || !isfinite(g->b_min) || !isfinite(g->b_max))
     return ORACLE_EINVAL;
@@ -158,6 +169,7 @@ static void prepare_hit(const oracle_grid* g, const float* phi_cs, const float* 
   h->s_phi = s_phi;
 
   int32_t pc[2], tc[2], nt = 0;
+  const int32_t np_cells = g->phi_sectors ? 1 : 2; /* O3': a sector holds the hit alone */
   pc[0] = s_phi >> 1;
   pc[1] = (s_phi & 1) ? (pc[0] + 1) % g->n_phi : (pc[0] - 1 + g->n_phi) % g->n_phi;
   tc[nt++] = s_th >> 1;
@@ -167,7 +179,7 @@ static void prepare_hit(const oracle_grid* g, const float* phi_cs, const float* 
   }
   h->n_cells = 0;
   for (int32_t a = 0; a < nt; ++a)
-    for (int32_t b = 0; b < 2; ++b) {
+    for (int32_t b = 0; b < np_cells; ++b) {
       h->cell_t[h->n_cells] = tc[a];
       h->cell_p[h->n_cells] = pc[b];
       h->n_cells++;
@@ -257,6 +269,7 @@ int64_t oracle_peaks(const oracle_grid* g, const uint32_t* M, uint32_t* out_cell
   const int64_t n_t = g->n_theta, n_p = g->n_phi, n_a = g->n_a, n_b = g->n_b;
   const int64_t cells = n_t * n_p * n_a * n_b;
   const uint32_t T = g->threshold;
+  const int dp_max = g->phi_sectors ? 0 : 1; /* O6': no neighbours across sectors */
   int64_t found = 0;
   for (int64_t c = 0; c < cells; ++c) {
     uint32_t v = M[c];
@@ -267,7 +280,7 @@ int64_t oracle_peaks(const oracle_grid* g, const uint32_t* M, uint32_t* out_cell
     int64_t t = c / (n_b * n_a * n_p);
     int is_peak = 1;
     for (int dt = -1; dt <= 1 && is_peak; ++dt)
-      for (int dp = -1; dp <= 1 && is_peak; ++dp)
+      for (int dp = -dp_max; dp <= dp_max && is_peak; ++dp)
         for (int da = -1; da <= 1 && is_peak; ++da)
           for (int db = -1; db <= 1 && is_peak; ++db) {
             if (dt == 0 && dp == 0 && da == 0 && db == 0) continue;

@@ -39,7 +39,7 @@ class _Grid(ctypes.Structure):
                 ("n_a", ctypes.c_int32), ("n_b", ctypes.c_int32),
                 ("a_min", ctypes.c_float), ("a_max", ctypes.c_float),
                 ("b_min", ctypes.c_float), ("b_max", ctypes.c_float),
-                ("threshold", ctypes.c_uint32)]
+                ("threshold", ctypes.c_uint32), ("phi_sectors", ctypes.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -53,6 +53,7 @@ class OracleGrid:
     b_min: float
     b_max: float
     threshold: int
+    phi_sectors: int = 0  # 1: independent phi sectors (paper section 4)
 
     @property
     def shape(self):
@@ -64,7 +65,7 @@ class OracleGrid:
 
     def _c(self) -> _Grid:
         return _Grid(self.n_theta, self.n_phi, self.n_a, self.n_b, self.a_min, self.a_max,
-                     self.b_min, self.b_max, self.threshold)
+                     self.b_min, self.b_max, self.threshold, int(self.phi_sectors))
 
 
 _lib = None

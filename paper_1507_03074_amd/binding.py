@@ -31,7 +31,7 @@ class Grid(ctypes.Structure):
                 ("n_a", ctypes.c_int32), ("n_b", ctypes.c_int32),
                 ("a_min", ctypes.c_float), ("a_max", ctypes.c_float),
                 ("b_min", ctypes.c_float), ("b_max", ctypes.c_float),
-                ("threshold", ctypes.c_uint32)]
+                ("threshold", ctypes.c_uint32), ("phi_sectors", ctypes.c_int32)]
 
     @property
     def shape(self):
@@ -158,7 +158,7 @@ def check(rc: int):
 
 def make_grid(spec) -> Grid:
     """Grid from a synth.GridSpec, a (n_theta, n_phi, n_a, n_b, a_min, a_max, b_min, b_max,
-    threshold) tuple, or a Grid."""
+    threshold[, phi_sectors]) tuple, or a Grid."""
     if isinstance(spec, Grid):
         return spec
     t = spec.as_tuple() if hasattr(spec, "as_tuple") else tuple(spec)

@@ -43,6 +43,7 @@ static const double kPi = 3.14159265358979323846;
 int validate_grid(const ht_grid* g)
 {
   if (!g) return fail(HT_EINVAL, "grid is NULL");
+  if (g->phi_sectors != 0) return fail(HT_EINVAL, "phi_sectors must be 0");
   if (g->n_theta < 1 || g->n_phi < 3 || g->n_a < 1 || g->n_b < 1)
     return fail(HT_EINVAL, "grid needs n_theta >= 1, n_phi >= 3, n_a >= 1, n_b >= 1");
   if (g->n_a > (1 << 24) || g->n_b > (1 << 24)) return fail(HT_EINVAL, "n_a and n_b must be <= 2^24");

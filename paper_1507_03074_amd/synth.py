@@ -38,6 +38,7 @@ class GridSpec:
     b_min: float = -2000.0
     b_max: float = 2000.0
     threshold: int = 9
+    phi_sectors: bool = False  # phi cells are independent sectors (paper section 4)
 
     @property
     def shape(self):
@@ -49,7 +50,7 @@ class GridSpec:
 
     def as_tuple(self):
         return (self.n_theta, self.n_phi, self.n_a, self.n_b, self.a_min, self.a_max,
-                self.b_min, self.b_max, self.threshold)
+                self.b_min, self.b_max, self.threshold, int(self.phi_sectors))
 
 
 @dataclass(frozen=True)

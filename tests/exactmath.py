@@ -98,7 +98,11 @@ def hit_cells_exact(grid, x, y, z):
     th = theta_angle(x, y, z)
     ph = phi_angle(x, y)
     tc = widened_cells(th, grid.n_theta, math.pi, periodic=False)
-    pc = widened_cells(ph, grid.n_phi, 2 * math.pi, periodic=True)
+    if getattr(grid, "phi_sectors", False):
+        # independent sectors: the one sector holding the azimuth, no widening
+        pc = [min(int(ph // (2 * math.pi / grid.n_phi)), grid.n_phi - 1)]
+    else:
+        pc = widened_cells(ph, grid.n_phi, 2 * math.pi, periodic=True)
     dist = min(boundary_distance(th, 2 * grid.n_theta, math.pi),
                boundary_distance(ph, 2 * grid.n_phi, 2 * math.pi),
                ph, 2 * math.pi - ph)
@@ -165,13 +169,15 @@ def brute_force_matrix(grid, x, y, z):
     return M
 
 
-def peaks_by_max_filter(M: np.ndarray, threshold: int):
+def peaks_by_max_filter(M: np.ndarray, threshold: int, phi_sectors: bool = False):
     """Peak cells from scipy's maximum filter on key = votes * 2^32 + (2^32 - 1 - index):
-    absent theta/A/B neighbours are padded with -1, phi wraps around."""
+    absent theta/A/B neighbours are padded with -1, phi wraps around; with phi_sectors the
+    window spans one phi cell (sectors have no phi neighbours)."""
     from scipy.ndimage import maximum_filter
     idx = np.arange(M.size, dtype=np.int64).reshape(M.shape)
     key = M.astype(np.int64) * (1 << 32) + ((1 << 32) - 1 - idx)
-    mx = maximum_filter(key, size=3, mode=["constant", "wrap", "constant", "constant"], cval=-1)
+    size = (3, 1, 3, 3) if phi_sectors else 3
+    mx = maximum_filter(key, size=size, mode=["constant", "wrap", "constant", "constant"], cval=-1)
     sel = (key == mx) & (M >= threshold)
     return np.flatnonzero(sel.ravel()).astype(np.uint32)
 

@@ -51,6 +51,12 @@ MUTANTS = [
     ("r2 with a minus", "float r2 = xx + yy;", "float r2 = xx - yy;"),
     ("readout phi not wrapped", "if (phi < 0.0) phi += 2.0 * kPi;", "(void)0;"),
     ("readout B at the bin edge", "((double)b + 0.5) * db", "((double)b) * db"),
+    ("sector keeps the widened phi cell", "const int32_t np_cells = g->phi_sectors ? 1 : 2;",
+     "const int32_t np_cells = 2;"),
+    ("sector peaks compare phi neighbours", "const int dp_max = g->phi_sectors ? 0 : 1;",
+     "const int dp_max = 1;"),
+    ("sector of the neighbouring half-sector", "pc[0] = s_phi >> 1;",
+     "pc[0] = g->phi_sectors ? ((s_phi + 1) >> 1) % g->n_phi : s_phi >> 1;"),
 ]
 
 

@@ -493,3 +493,114 @@ def test_readout_matches_definition(oracle_mod, spec):
         assert r["phi"][i] == pytest.approx(phi, abs=1e-12)
         assert 0.0 <= r["phi"][i] < 2 * math.pi
         assert r["theta"][i] == pytest.approx((t[i] + 0.5) * math.pi / spec.n_theta, rel=1e-14)
+
+
+# ---------------------------------------------------------------------------------------------
+# Sector variant (paper section 4): independent phi sectors, one M_H(A, B, theta) each
+# ---------------------------------------------------------------------------------------------
+def sectors(spec, n_phi=None):
+    return synth.GridSpec(spec.n_theta, n_phi or spec.n_phi, spec.n_a, spec.n_b, spec.a_min,
+                          spec.a_max, spec.b_min, spec.b_max, spec.threshold, phi_sectors=True)
+
+
+@pytest.mark.pin
+@pytest.mark.parametrize("spec", [sectors(CFG0), sectors(CFG0, 4), sectors(RAGGED, 1),
+                                  sectors(RAGGED, 2)])
+def test_sector_cells_match_atan2(oracle_mod, spec):
+    rng = np.random.default_rng(21)
+    x, y, z = random_hits(rng, 2000)
+    info = oracle_mod.hit_info(og(oracle_mod, spec), x, y, z)
+    checked = 0
+    for h in range(x.size):
+        cells, dist = em.hit_cells_exact(spec, x[h], y[h], z[h])
+        if dist < 1e-5:
+            continue
+        checked += 1
+        got = sorted((int(t), int(p)) for t, p in info["cells"][h] if t >= 0)
+        assert got == cells, (h, got, cells)
+        # one sector per hit; theta cells as in the 4-D transform
+        assert len({p for _, p in got}) == 1
+    assert checked > 0.99 * x.size
+
+
+@pytest.mark.pin
+@pytest.mark.parametrize("spec", [sectors(TINY), sectors(RAGGED, 2)])
+def test_sector_fill_equals_brute_force(oracle_mod, spec):
+    rng = np.random.default_rng(5)
+    x, y, z = safe_hits(spec, rng, 24)
+    M, votes = oracle_mod.fill(og(oracle_mod, spec), x, y, z)
+    ref = em.brute_force_matrix(spec, x, y, z)
+    assert np.array_equal(M, ref)
+    assert votes == int(ref.sum())
+
+
+@pytest.mark.pin
+@pytest.mark.parametrize("spec", [CFG0, RAGGED])
+def test_sector_votes_are_a_half_of_the_4d_votes(oracle_mod, spec):
+    """Every valid hit votes in two phi cells of the 4-D transform and in one sector, with the
+    same (A, B) line, so the totals differ by exactly a factor 2, and each sector's matrix is
+    bounded cell by cell by the same slab of the 4-D matrix (its hits are a subset)."""
+    g4, gs = og(oracle_mod, spec), og(oracle_mod, sectors(spec))
+    for e in range(6):
+        ev = synth.make_event(0, 40 + e)
+        M4, v4 = oracle_mod.fill(g4, ev.x, ev.y, ev.z)
+        Ms, vs = oracle_mod.fill(gs, ev.x, ev.y, ev.z)
+        assert v4 == 2 * vs > 0
+        assert int(M4.sum(dtype=np.int64)) == 2 * int(Ms.sum(dtype=np.int64))
+        assert np.all(Ms <= M4)
+        i4 = oracle_mod.hit_info(g4, ev.x, ev.y, ev.z)
+        i_s = oracle_mod.hit_info(gs, ev.x, ev.y, ev.z)
+        assert np.array_equal(i4["n_cells"], 2 * i_s["n_cells"])
+        # the sector of a hit is the phi cell its own half-sector lies in
+        own = i4["s_phi"] // 2
+        for h in np.flatnonzero(i_s["valid"]):
+            assert {int(p) for t, p in i_s["cells"][h] if t >= 0} == {int(own[h])}
+
+
+@pytest.mark.pin
+@pytest.mark.parametrize("shape", [(2, 4, 8, 8), (3, 5, 7, 9), (2, 1, 6, 5), (3, 2, 4, 1)])
+def test_sector_peaks_match_maximum_filter(oracle_mod, shape):
+    rng = np.random.default_rng(100 + sum(shape))
+    spec = synth.GridSpec(*shape, threshold=3, phi_sectors=True)
+    M = tie_heavy_matrix(rng, shape)
+    cells, vv, n = oracle_mod.peaks(og(oracle_mod, spec), M)
+    ref = em.peaks_by_max_filter(M, 3, phi_sectors=True)
+    assert n == ref.size
+    assert np.array_equal(cells, ref)
+    assert np.array_equal(vv, M.ravel()[ref])
+    # a sector peak list is the merge of the per-sector 3-D searches
+    per = []
+    for p in range(shape[1]):
+        sub = np.ascontiguousarray(M[:, p:p + 1])
+        c3, _, _ = oracle_mod.peaks(og(oracle_mod, synth.GridSpec(shape[0], 1, shape[2], shape[3],
+                                                                  threshold=3, phi_sectors=True)), sub)
+        tt, _, aa, bb = np.unravel_index(c3.astype(np.int64), (shape[0], 1, shape[2], shape[3]))
+        per.extend(np.ravel_multi_index((tt, np.full_like(tt, p), aa, bb), shape).tolist())
+    assert sorted(per) == cells.tolist()
+
+
+@pytest.mark.pin
+def test_sector_grid_limits(oracle_mod):
+    base = dict(n_theta=2, n_a=4, n_b=4, a_min=-1.0, a_max=1.0, b_min=-1.0, b_max=1.0, threshold=1)
+    assert oracle_mod.check_grid(oracle_mod.OracleGrid(n_phi=1, phi_sectors=1, **base))
+    assert oracle_mod.check_grid(oracle_mod.OracleGrid(n_phi=2, phi_sectors=1, **base))
+    assert not oracle_mod.check_grid(oracle_mod.OracleGrid(n_phi=2, phi_sectors=0, **base))
+    assert not oracle_mod.check_grid(oracle_mod.OracleGrid(n_phi=4, phi_sectors=2, **base))
+
+
+@pytest.mark.pin
+def test_sector_single_track_peak(oracle_mod):
+    """A noiseless track whose hits all lie in one sector: its generating cell holds one vote
+    per layer and is the only peak."""
+    spec = synth.GridSpec(4, 4, 64, 64, threshold=12, phi_sectors=True)
+    g = og(oracle_mod, spec)
+    rng = np.random.default_rng(8)
+    for _ in range(5):
+        x, y, z, (a0, b0), common = single_track_case(spec, rng)
+        assert len({p for _, p in common}) == 1
+        M, _ = oracle_mod.fill(g, x, y, z)
+        for t, p in common:
+            assert M[t, p, a0, b0] == 12
+        cells, vv, n = oracle_mod.peaks(g, M)
+        t_star, p_star = common[0]
+        assert n == 1 and int(cells[0]) == np.ravel_multi_index((t_star, p_star, a0, b0), spec.shape)
