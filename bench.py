@@ -366,6 +366,73 @@ def counter_traffic(tuning: dict):
     return None
 
 
+def bench_sectors(B, torch, synth, evs, dev_hits, steps):
+    """The sector variant (paper section 4) on the paper-shaped events: four phi sectors, one
+    M_H(A, B, theta) each (4 x 4 x 1024 x 1024, 64 MiB), through the plain per-event path, and
+    its track finding next to the 4-D transform's (16 widened phi cells) on the same events."""
+    from paper_1507_03074_amd import physics
+    spec4 = synth.WORKLOADS[1].grid
+    specS = synth.GridSpec(4, 4, 1024, 1024, threshold=spec4.threshold, phi_sectors=True)
+    stream = torch.cuda.current_stream()
+    cap = 4096
+    acc = B.new_acc(specS)
+    out, nf = B.new_peaks(cap)
+    n = len(dev_hits)
+    for k in range(20):
+        x, y, z = dev_hits[k % n]
+        B.ht_fill_peaks(specS, x, y, z, acc, out, cap, nf, stream)
+    torch.cuda.synchronize()
+    B.ht_profile_read("fill", reset=True)
+    B.ht_profile_enable(2)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        x, y, z = dev_hits[k % n]
+        B.ht_fill_peaks(specS, x, y, z, acc, out, cap, nf, stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    B.ht_profile_enable(0)
+    fill_ms, fill_n = B.ht_profile_read("fill", reset=True)
+    res = {"grid": list(specS.shape), "matrix_MiB": specS.n_cells * 4 >> 20,
+           "ms_per_event": round(dt * 1e3, 4), "events_per_s": round(1.0 / dt, 1),
+           "fill_us": round(fill_ms / max(fill_n, 1) * 1e3, 2)}
+    # track finding: sectors against the 4-D transform on the same events
+    acc4 = B.new_acc(spec4)
+    out4, nf4 = B.new_peaks(cap)
+    cmp = {"events": 0, "in_acceptance": 0, "found_4d": 0, "found_sectors": 0,
+           "lost_in_sectors": 0, "lost_in_sectors_crossing_a_sector_edge": 0,
+           "gained_in_sectors": 0, "peaks_4d": 0, "peaks_sectors": 0}
+    for i in range(min(8, n)):
+        x, y, z = dev_hits[i]
+        B.ht_fill_peaks(spec4, x, y, z, acc4, out4, cap, nf4, stream)
+        B.ht_fill_peaks(specS, x, y, z, acc, out, cap, nf, stream)
+        t4 = B.tracks_to_host(B.ht_readout(spec4, out4, nf4, cap), nf4, cap)
+        tS = B.tracks_to_host(B.ht_readout(specS, out, nf, cap), nf, cap)
+        e4 = physics.evaluate(spec4, t4, evs[i])
+        eS = physics.evaluate(specS, tS, evs[i])
+        f4, fS = set(e4["found_ids"]), set(eS["found_ids"])
+        ev = evs[i]
+        crossing = 0
+        for k in f4 - fS:
+            own = ev.track_of_hit == k
+            ph = np.mod(np.arctan2(ev.y[own].astype(np.float64), ev.x[own].astype(np.float64)), 2 * np.pi)
+            crossing += len(set(np.floor(ph / (np.pi / 2)).astype(int).tolist())) > 1
+        cmp["events"] += 1
+        cmp["in_acceptance"] += e4["in_acceptance"]
+        cmp["found_4d"] += len(f4)
+        cmp["found_sectors"] += len(fS)
+        cmp["lost_in_sectors"] += len(f4 - fS)
+        cmp["lost_in_sectors_crossing_a_sector_edge"] += crossing
+        cmp["gained_in_sectors"] += len(fS - f4)
+        cmp["peaks_4d"] += e4["peaks"]
+        cmp["peaks_sectors"] += eS["peaks"]
+    cmp["efficiency_4d"] = round(cmp["found_4d"] / max(1, cmp["in_acceptance"]), 4)
+    cmp["efficiency_sectors"] = round(cmp["found_sectors"] / max(1, cmp["in_acceptance"]), 4)
+    res["vs_4d"] = cmp
+    del acc, acc4
+    torch.cuda.empty_cache()
+    return res
+
+
 def ctypes_stream(stream):
     import ctypes
     return ctypes.c_void_p(stream.cuda_stream)
@@ -589,6 +656,8 @@ def main():
         stream.synchronize()
         lat.append((time.perf_counter() - ts) * 1e3)
     line["plain_latency_ms"] = {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)}
+    log("sector variant")
+    line["sectors"] = bench_sectors(B, torch, synth, evs, dev_hits, min(args.steps, 300))
     if not args.quick:
         del acc, out
         torch.cuda.empty_cache()

@@ -43,9 +43,9 @@ static const double kPi = 3.14159265358979323846;
 int validate_grid(const ht_grid* g)
 {
   if (!g) return fail(HT_EINVAL, "grid is NULL");
-  if (g->phi_sectors != 0) return fail(HT_EINVAL, "phi_sectors must be 0");
-  if (g->n_theta < 1 || g->n_phi < 3 || g->n_a < 1 || g->n_b < 1)
-    return fail(HT_EINVAL, "grid needs n_theta >= 1, n_phi >= 3, n_a >= 1, n_b >= 1");
+  if (g->phi_sectors != 0 && g->phi_sectors != 1) return fail(HT_EINVAL, "phi_sectors must be 0 or 1");
+  if (g->n_theta < 1 || g->n_phi < (g->phi_sectors ? 1 : 3) || g->n_a < 1 || g->n_b < 1)
+    return fail(HT_EINVAL, "grid needs n_theta >= 1, n_phi >= 3 (>= 1 with phi sectors), n_a >= 1, n_b >= 1");
   if (g->n_a > (1 << 24) || g->n_b > (1 << 24)) return fail(HT_EINVAL, "n_a and n_b must be <= 2^24");
   if ((int64_t)g->n_theta * g->n_phi > kMaxSlabs) return fail(HT_EINVAL, "n_theta*n_phi must be <= 4096");
   if (!std::isfinite(g->a_min) || !std::isfinite(g->a_max) || !std::isfinite(g->b_min) ||
@@ -267,6 +267,7 @@ DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
   d.group_tiles = tl.group_tiles;
   d.nt_store = tl.nt_store;
   d.fill_tiles = tl.fill_tiles;
+  d.phi_sectors = g.phi_sectors;
   // candidate test: enough workgroups to spread a few thousand candidates over the whole chip
   // in one pass (two candidates per wave), few enough that a near-empty event exits at once
   d.test_blocks = std::max(16, std::min(1024, (tl.n_tiles + 15) / 16));

@@ -46,6 +46,7 @@ struct DevGrid {
   int32_t group_tiles;     // tiles per workgroup of the peak search (16, 32 or 64)
   int32_t nt_store;        // fill store kind: 0 16-byte, 1 non-temporal 16-byte, 2 4-byte
   int32_t fill_tiles;      // fill tiles per workgroup (filled in turn)
+  int32_t phi_sectors;     // 1: phi cells are independent sectors (no phi widening or neighbours)
   int32_t test_blocks;     // workgroups per event of the candidate test
   const float* a2;         // device [n_a]
   const float* phi_cs;     // device [2 * 2 n_phi] (cos, sin)

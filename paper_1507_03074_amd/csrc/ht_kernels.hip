@@ -208,13 +208,23 @@ __device__ HitPrep prep_hit(const DevGrid& g, float x, float y, float z)
   const int p1 = (s_phi & 1) ? (p0 + 1 == g.n_phi ? 0 : p0 + 1) : (p0 == 0 ? g.n_phi - 1 : p0 - 1);
   const int t0 = s_th >> 1;
   const int t1 = (s_th & 1) ? t0 + 1 : t0 - 1;
-  h.slab[0] = t0 * g.n_phi + p0;
-  h.slab[1] = t0 * g.n_phi + p1;
-  h.n = 2;
-  if (t1 >= 0 && t1 < g.n_theta) {
-    h.slab[2] = t1 * g.n_phi + p0;
-    h.slab[3] = t1 * g.n_phi + p1;
-    h.n = 4;
+  if (g.phi_sectors) {
+    // section 4: the hit's own sector only
+    h.slab[0] = t0 * g.n_phi + p0;
+    h.n = 1;
+    if (t1 >= 0 && t1 < g.n_theta) {
+      h.slab[1] = t1 * g.n_phi + p0;
+      h.n = 2;
+    }
+  } else {
+    h.slab[0] = t0 * g.n_phi + p0;
+    h.slab[1] = t0 * g.n_phi + p1;
+    h.n = 2;
+    if (t1 >= 0 && t1 < g.n_theta) {
+      h.slab[2] = t1 * g.n_phi + p0;
+      h.slab[3] = t1 * g.n_phi + p1;
+      h.n = 4;
+    }
   }
   h.s_theta = s_th;
   h.s_phi = s_phi;
@@ -609,6 +619,7 @@ __device__ bool is_peak(const DevGrid& g, const uint32_t* __restrict__ acc, uint
       const int dt = k / 9 - 1, dp = (k / 3) % 3 - 1, da = k % 3 - 1;
       const int tt = (int)t + dt, aa = (int)a + da;
       if (tt < 0 || tt >= g.n_theta || aa < 0 || aa >= (int)na) continue;
+      if (g.phi_sectors && dp != 0) continue;
       const uint32_t pp = dp < 0 ? pm : (dp > 0 ? pp1 : p);
       const uint32_t rowc = (((uint32_t)tt * np + pp) * na + (uint32_t)aa) * nb;
       for (int db = -1; db <= 1; ++db) {
@@ -629,7 +640,7 @@ __device__ bool is_peak(const DevGrid& g, const uint32_t* __restrict__ acc, uint
   for (int k = 0; k < 27; ++k) {
     const int dt = k / 9 - 1, dp = (k / 3) % 3 - 1, da = k % 3 - 1;
     const int tt = (int)t + dt, aa = (int)a + da;
-    rv[k] = tt >= 0 && tt < g.n_theta && aa >= 0 && aa < (int)na;
+    rv[k] = tt >= 0 && tt < g.n_theta && aa >= 0 && aa < (int)na && !(g.phi_sectors && dp != 0);
     const uint32_t pp = dp < 0 ? pm : (dp > 0 ? pp1 : p);
     base[k] = (rv[k] ? (((uint32_t)tt * np + pp) * na + (uint32_t)aa) * nb : c - b) + w0;
     const GLOBAL uint32_t* rw = gp(acc) + base[k];
@@ -708,6 +719,7 @@ __device__ bool row_beats(const DevGrid& g, const uint32_t* __restrict__ acc, ui
   const int dt = k / 9 - 1, dp = (k / 3) % 3 - 1, da = k % 3 - 1;
   const int tt = (int)t + dt, aa = (int)a + da;
   if (tt < 0 || tt >= g.n_theta || aa < 0 || aa >= (int)na) return false;
+  if (g.phi_sectors && dp != 0) return false;  // sectors have no phi neighbours
   const uint32_t pp = dp < 0 ? (p == 0 ? np - 1 : p - 1) : (dp > 0 ? (p + 1 == np ? 0 : p + 1) : p);
   const uint32_t rowc = (((uint32_t)tt * np + pp) * na + (uint32_t)aa) * nb;
   const bool centre_row = k == 13;

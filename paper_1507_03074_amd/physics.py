@@ -51,6 +51,7 @@ def evaluate(spec, tracks, ev, window: int = 1):
            & (counts == synth.LAYER_RADII_MM.size))
     used = np.zeros(len(tracks), bool)
     found, d_rho_ht, d_phi_ht, d_rho_fit, d_phi_fit = 0, [], [], [], []
+    found_ids = []
     for k in np.flatnonzero(acc):
         m = ((np.abs(tracks["a"] - a_true[k]) <= window) & (np.abs(tracks["b"] - b_true[k]) <= window)
              & (np.abs(tracks["t"] - t_true[k]) <= 1))
@@ -63,6 +64,7 @@ def evaluate(spec, tracks, ev, window: int = 1):
         if not m.any():
             continue
         found += 1
+        found_ids.append(int(k))
         used |= m
         best = np.flatnonzero(m)[np.argmax(tracks["votes"][m])]
         d_rho_ht.append((float(tracks["rho"][best]) - rho_t) / rho_t)
@@ -78,4 +80,5 @@ def evaluate(spec, tracks, ev, window: int = 1):
             "fake_rate": float((~used).mean()) if len(tracks) else None,
             "rho_resolution_ht": rms(d_rho_ht), "phi_resolution_ht": rms(d_phi_ht),
             "rho_resolution_fit": rms(d_rho_fit), "phi_resolution_fit": rms(d_phi_fit),
-            "bin_width_rel_rho": dA / 1000.0}
+            "bin_width_rel_rho": dA / 1000.0, "found_ids": found_ids,
+            "acceptance_ids": [int(k) for k in np.flatnonzero(acc)]}

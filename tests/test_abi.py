@@ -156,3 +156,19 @@ def test_profile_modes_validated_on_host(lib):
     for mode in (-1, 3):
         assert lib.ht_profile_enable(mode) == B.HT_EINVAL
     assert lib.ht_profile_enable(0) == 0
+
+
+def test_sector_grids_validated_on_host(lib):
+    """phi_sectors is 0 or 1; with sectors n_phi may be 1 or 2; the tables do not depend on it."""
+    from oracle import oracle
+    dummy = ctypes.c_void_p(256)
+    g = B.make_grid(synth.GridSpec(4, 4, 64, 64, phi_sectors=True))
+    g.phi_sectors = 2
+    assert lib.ht_fill(ctypes.byref(g), None, None, None, 0, dummy, None) == B.HT_EINVAL
+    assert "phi_sectors" in B.last_error()
+    for n_phi in (1, 2, 4):
+        spec = synth.GridSpec(3, n_phi, 16, 8, threshold=2, phi_sectors=True)
+        a2, inv, uphi, uth = B.ht_tables(spec)
+        oa2, oinv, ouphi, outh = oracle.tables(oracle.OracleGrid(*spec.as_tuple()))
+        assert a2.tobytes() == oa2.tobytes() and uphi.tobytes() == ouphi.tobytes()
+        assert B.ht_tiling(spec)["n_tiles"] >= 3 * n_phi

@@ -572,3 +572,96 @@ def test_alternating_grid_sizes_keep_counters_clean(gpu):
         gM, gc, gv, gn = gpu_fused(B, spec, x, y, z)
         M, votes, oc, ov, on = oracle_run(spec, x, y, z)
         assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "call %d" % k)
+
+
+# ---------------------------------------------------------------------------------------------
+# Sector variant (paper section 4): phi cells are independent sectors
+# ---------------------------------------------------------------------------------------------
+def sector_grid(spec, n_phi):
+    return synth.GridSpec(spec.n_theta, n_phi, spec.n_a, spec.n_b, spec.a_min, spec.a_max,
+                          spec.b_min, spec.b_max, spec.threshold, phi_sectors=True)
+
+
+SECTOR_GRIDS = [sector_grid(CFG0, 4), sector_grid(CFG0, 16), sector_grid(CFG0, 1),
+                synth.GridSpec(3, 2, 7, 9, a_min=-1500.0, a_max=1300.0, b_min=-1100.0, b_max=1700.0,
+                               threshold=2, phi_sectors=True),
+                synth.GridSpec(2, 4, 3, 20000, threshold=2, phi_sectors=True)]  # atomic fill
+
+
+@pytest.mark.parametrize("spec", SECTOR_GRIDS, ids=lambda s: "x".join(map(str, s.shape)))
+def test_sector_events_bit_exact(gpu, spec):
+    """Fused fill + peaks, the separate fills and ht_peaks, in sector mode."""
+    import torch
+    B = gpu
+    for e in range(6):
+        ev = synth.make_event(0, 700 + e)
+        x, y, z = (ev.x, ev.y, ev.z) if spec.n_b < 10000 else (ev.x[:60], ev.y[:60], ev.z[:60])
+        say("sector grid", spec.shape, "event", e)
+        gM, gc, gv, gn = gpu_fused(B, spec, x, y, z)
+        M, votes, oc, ov, on = oracle_run(spec, x, y, z)
+        assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "event %d" % e)
+        xd, yd, zd = B.hits_to_device(x, y, z)
+        a1 = B.fill(spec, xd, yd, zd)
+        a2 = B.fill(spec, xd, yd, zd, atomic=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(B.as_u32(a1), M) and np.array_equal(B.as_u32(a2), M)
+        c, v, n = B.peaks(spec, a1)
+        assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
+
+
+def test_sector_hit_values_match_oracle(gpu):
+    import torch
+    from oracle import oracle
+    B = gpu
+    rng = np.random.default_rng(12)
+    x, y, z = synth.uniform_hits(rng, 50000, 1000.0, 2500.0)
+    for spec in (sector_grid(CFG0, 4), sector_grid(CFG0, 1), sector_grid(CFG4, 2)):
+        say("sector hit values: grid", spec.shape)
+        xd, yd, zd = B.hits_to_device(x, y, z)
+        info, vals, slabs = B.ht_debug_hit_values(spec, xd, yd, zd)
+        torch.cuda.synchronize()
+        info, slabs = info.cpu().numpy(), slabs.cpu().numpy()
+        o = oracle.hit_info(oracle.OracleGrid(*spec.as_tuple()), x, y, z)
+        assert np.array_equal(info[:, 3], o["n_cells"])
+        oslab = np.where(o["cells"][:, :, 0] >= 0, o["cells"][:, :, 0] * spec.n_phi + o["cells"][:, :, 1], -1)
+        assert np.array_equal(slabs, oslab)
+
+
+@pytest.mark.parametrize("shape,T", [((2, 4, 8, 8), 3), ((3, 1, 7, 9), 3), ((4, 4, 64, 64), 4),
+                                     ((2, 2, 40, 130), 5)])
+def test_sector_peaks_on_arbitrary_matrices(gpu, shape, T):
+    import torch
+    from oracle import oracle
+    B = gpu
+    say("sector peaks on a random matrix", shape)
+    rng = np.random.default_rng(sum(shape) + 7 * T)
+    M = rng.integers(0, 4, size=shape).astype(np.uint32)
+    spikes = rng.random(shape) < 0.03
+    M[spikes] += rng.integers(3, 12, size=int(spikes.sum())).astype(np.uint32)
+    spec = synth.GridSpec(*shape, threshold=T, phi_sectors=True)
+    acc = torch.from_numpy(M.view(np.int32).copy()).cuda()
+    c, v, n = B.peaks(spec, acc)
+    oc, ov, on = oracle.peaks(oracle.OracleGrid(*spec.as_tuple()), M)
+    assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
+
+
+def test_sector_paper_grid_and_batch(gpu):
+    """The paper's four sectors on the paper-shaped workload: single events and one batch."""
+    B = gpu
+    spec = sector_grid(CFG1, 4)
+    hits = []
+    for e in range(3):
+        ev = synth.make_event(1, 30 + e)
+        say("sector paper grid, event", e)
+        gM, gc, gv, gn = gpu_fused(B, spec, ev.x, ev.y, ev.z)
+        M, votes, oc, ov, on = oracle_run(spec, ev.x, ev.y, ev.z)
+        assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "event %d" % e)
+        hits.append((ev.x, ev.y, ev.z))
+    say("sector paper grid, batch of 3")
+    res = B.fill_peaks_batch(spec, hits, capacity=1 << 14)
+    accs = B.as_u32(res.acc)
+    for i, (x, y, z) in enumerate(hits):
+        M, votes, oc, ov, on = oracle_run(spec, x, y, z)
+        assert np.array_equal(accs[i], M), i
+        c, v, n = res.peaks[i]
+        assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov), i
