@@ -147,10 +147,19 @@ def measure_peaks(B, torch, acc_bytes, big_bytes=2 << 30):
             "lds_atomic_Gops": round(blocks * 256 * iters / t_l / 1e9, 1)}
 
 
-def bench_batched(B, torch, synth, workload, n_events, reps, capacity):
-    """One ht_fill_peaks_batch call (a captured graph) over n_events events of the workload."""
+def bench_batched(B, torch, synth, workload, n_events, reps, capacity, tune_batch=False):
+    """One ht_fill_peaks_batch call (a captured graph) over n_events events of the workload;
+    with tune_batch, the launch shape comes from the autotuner run on this batch (and the grid's
+    previous shape is restored afterwards)."""
     spec = synth.WORKLOADS[workload].grid
     evs = [synth.make_event(workload, e) for e in range(n_events)]
+    tuned = None
+    if tune_batch:
+        from paper_1507_03074_amd import tune
+        before = B.ht_get_tuning(spec)
+        rep = tune.autotune_batch(spec, [(e.x, e.y, e.z) for e in evs], capacity=capacity)
+        tuned = {"best": rep["best"], "default_ms_per_batch": round(rep["default_ms_per_batch"], 3),
+                 "candidates": len(rep["candidates"])}
     xs = np.concatenate([e.x for e in evs])
     ys = np.concatenate([e.y for e in evs])
     zs = np.concatenate([e.z for e in evs])
@@ -176,7 +185,10 @@ def bench_batched(B, torch, synth, workload, n_events, reps, capacity):
            "gvotes_per_s": round(votes / dt / 1e9, 2),
            "hbm_write_GBs": round(4 * spec.n_cells * n_events / dt / 1e9, 1),
            "peaks_per_event": round(float(nf.float().mean().item()), 1),
-           "max_peaks": int(nf.max().item()), "capacity": capacity}
+           "max_peaks": int(nf.max().item()), "capacity": capacity,
+           "tuning": B.ht_get_tuning(spec).as_dict(), "autotune": tuned}
+    if tune_batch:
+        B.ht_set_tuning(spec, before)
     del acc, out, x, y, z
     torch.cuda.empty_cache()
     return res
@@ -662,7 +674,7 @@ def main():
         del acc, out
         torch.cuda.empty_cache()
         log("batched workload 2")
-        line["batched"] = bench_batched(B, torch, synth, 2, 100, 5, 1 << 13)
+        line["batched"] = bench_batched(B, torch, synth, 2, 100, 5, 1 << 13, tune_batch=True)
         log("stress workload 4")
         line["stress"] = bench_batched(B, torch, synth, 4, 16, 3, 1 << 21)
         log("transfer study")

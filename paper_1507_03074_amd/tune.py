@@ -110,6 +110,84 @@ def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool 
             "best": best, "candidates": results}
 
 
+def autotune_batch(spec, events, reps: int = 3, capacity: int = 1 << 13, apply: bool = True):
+    """The same search for one batched launch (ht_fill_peaks_batch) over `events` (host (x, y, z)
+    tuples): a batch's matrices usually exceed the last-level cache, where another store kind
+    than a single event's can win. Every candidate's matrices and peak lists must equal the
+    default shape's bit for bit."""
+    import torch
+    xs = np.concatenate([np.asarray(e[0], np.float32) for e in events])
+    ys = np.concatenate([np.asarray(e[1], np.float32) for e in events])
+    zs = np.concatenate([np.asarray(e[2], np.float32) for e in events])
+    x, y, z = B.hits_to_device(xs, ys, zs)
+    evs, off = [], 0
+    for i, e in enumerate(events):
+        evs.append(B.Event(off, len(e[0]), i * capacity, capacity))
+        off += len(e[0])
+    n = len(events)
+    acc = B.new_acc(spec, n)
+    out = torch.empty((n * capacity, 2), dtype=torch.int32, device="cuda")
+    nf = torch.zeros(n, dtype=torch.int64, device="cuda")
+
+    def run():
+        B.ht_fill_peaks_batch(spec, evs, x, y, z, acc, out, nf)
+
+    def timed():
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    B.ht_set_tuning(spec)
+    run()
+    torch.cuda.synchronize()
+    ref_acc, ref_out, ref_nf = acc.clone(), out.clone(), nf.clone()
+    t_default = timed()
+    results = []
+
+    def trial(cand):
+        try:
+            B.ht_set_tuning(spec, cand)
+        except B.HTError:
+            return
+        cand = B.ht_get_tuning(spec)
+        acc.zero_()
+        run()
+        torch.cuda.synchronize()
+        exact = bool(torch.equal(nf, ref_nf) and torch.equal(acc, ref_acc))
+        if exact:
+            for i in range(n):
+                k = min(int(ref_nf[i]), capacity)
+                seg = slice(i * capacity, i * capacity + k)
+                if not torch.equal(out[seg], ref_out[seg]):
+                    exact = False
+                    break
+        t = timed() if exact else None
+        results.append({"tuning": cand.as_dict(), "ms_per_batch": None if t is None else t * 1e3,
+                        "bit_exact": exact})
+
+    for cand in candidates(spec):
+        trial(cand)
+    ok = [r for r in results if r["bit_exact"]]
+    if ok:
+        f = min(ok, key=lambda r: r["ms_per_batch"])["tuning"]
+        for gt in (16, 32, 64):
+            if gt != f["group_tiles"]:
+                trial(B.Tuning(f["rows"], gt, 0, f["nt_store"], f["tiles_per_block"]))
+    B.ht_set_tuning(spec)
+    ok = [r for r in results if r["bit_exact"]]
+    best = min(ok, key=lambda r: r["ms_per_batch"]) if ok else None
+    if apply and best:
+        B.ht_set_tuning(spec, B.Tuning(**best["tuning"]))
+    del acc, out, nf, ref_acc, ref_out, ref_nf, x, y, z
+    torch.cuda.empty_cache()
+    return {"grid": grid_key(spec), "arch": arch_name(), "events": n,
+            "default_ms_per_batch": t_default * 1e3, "best": best, "candidates": results}
+
+
 def save(report, path: str = DEFAULT_CACHE):
     cache = {}
     if os.path.exists(path):

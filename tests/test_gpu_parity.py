@@ -665,3 +665,25 @@ def test_sector_paper_grid_and_batch(gpu):
         assert np.array_equal(accs[i], M), i
         c, v, n = res.peaks[i]
         assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov), i
+
+
+def test_batch_autotuner_keeps_results(gpu):
+    from paper_1507_03074_amd import tune
+    B = gpu
+    evs = [synth.make_event(0, 900 + e) for e in range(12)]
+    say("autotune a workload-0 batch")
+    before = B.ht_get_tuning(CFG0).as_dict()
+    rep = tune.autotune_batch(CFG0, [(e.x, e.y, e.z) for e in evs], reps=2, capacity=256)
+    try:
+        assert rep["best"] is not None and all(c["bit_exact"] for c in rep["candidates"])
+        assert B.ht_get_tuning(CFG0).as_dict() == rep["best"]["tuning"]
+        res = B.fill_peaks_batch(CFG0, [(e.x, e.y, e.z) for e in evs], capacity=256)
+        accs = B.as_u32(res.acc)
+        for i, e in enumerate(evs):
+            M, votes, oc, ov, on = oracle_run(CFG0, e.x, e.y, e.z)
+            assert np.array_equal(accs[i], M)
+            c, v, n = res.peaks[i]
+            assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
+    finally:
+        B.ht_set_tuning(CFG0)
+    assert B.ht_get_tuning(CFG0).as_dict() == before
