@@ -357,24 +357,25 @@ def bench_transfers(B, torch, synth, spec, sizes=(500, 1000, 2000, 4000, 8000), 
 def counter_traffic(tuning: dict):
     """HBM bytes per fill launch from the committed FETCH_SIZE / WRITE_SIZE counter summary
     (each counter scaled by what it reads for a copy of known size), or None when the summary
-    was taken on other kernel sources or another launch shape."""
+    was taken on other kernel sources or with another fill shape (A rows per tile, store kind,
+    tiles per workgroup)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "k_fill_paper-event_counters.md")
     src = os.path.join(ROOT, "paper_1507_03074_amd", "csrc", "ht_kernels.hip")
     try:
         text = open(path).read()
-        m = re.search(r"```json\n(.*?)\n```", text, re.S)
-        rec = json.loads(m.group(1))
+        recs = [json.loads(m) for m in re.findall(r"```json\n(.*?)\n```", text, re.S)]
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except (OSError, AttributeError, ValueError):
+    except (OSError, ValueError):
         return None
-    shape = ",".join(str(tuning[f]) for f in ("rows", "group_tiles", "cand_cap", "nt_store", "tiles_per_block"))
-    if rec.get("kernels_source_sha256") != sha or rec.get("tuning") != shape:
-        return None
-    for name, v in rec["per_launch"].items():
-        if name.startswith("k_fill<%d," % tuning["rows"]):
-            return v["traffic_bytes"]
+    shape = [tuning[f] for f in ("rows", "nt_store", "tiles_per_block")]
+    for rec in recs:
+        if rec.get("kernels_source_sha256") != sha or rec.get("fill_shape") != shape:
+            continue
+        for name, v in rec["per_launch"].items():
+            if name.startswith("k_fill<%d," % tuning["rows"]):
+                return v["traffic_bytes"]
     return None
 
 
