@@ -352,10 +352,11 @@ __global__ __launch_bounds__(kBlock) void k_bucket(DevGrid g, EvDesc ev0, const 
 // Candidates (cells >= threshold) of one tile, from the tile's counts in LDS: the tile reserves
 // a chunk of the event's candidate pool with one atomic, then each wave writes the candidates
 // of its quarter of the tile in cell order (ballot compaction), so every tile's chunk is sorted
-// by cell index, and clears them in LDS. A tile whose candidates do not fit the pool is marked
-// overflowed.
+// by cell index, and clears them in LDS. A tile whose candidates do not fit the pool is
+// recorded as overflowed (searched densely). (Dropping here the cells that lose to a neighbour
+// inside the tile cut the peak test but cost the fill more than it saved.)
 // Called by the whole block; `any` is nonzero iff the tile holds a candidate (a block-uniform
-// hint from the flush; the reservation uses this function's own count); s_small: >= 9 words.
+// hint; the reservation uses this function's own count); s_small: >= 9 words.
 // ---------------------------------------------------------------------------------------------
 __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uint32_t cell0,
                                 uint32_t* s_tile, uint32_t L, uint32_t any, uint32_t* s_small)
@@ -376,11 +377,12 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
   }
   const uint32_t seg = (L + 3u) / 4u;
   const uint32_t s0 = min(L, (uint32_t)wave * seg), s1 = min(L, s0 + seg);
+  auto is_cand = [&](uint32_t i, uint32_t v) { return i < s1 && v >= T; };
   uint32_t cnt = 0;
   for (uint32_t b = s0; b < s1; b += 64) {
     const uint32_t i = b + lane;
-    const bool c = i < s1 && s_tile[i] >= T;
-    cnt += (uint32_t)__popcll(__ballot(c));
+    const uint32_t v = i < s1 ? s_tile[i] : 0u;
+    cnt += (uint32_t)__popcll(__ballot(is_cand(i, v)));
   }
   if (lane == 0) s_small[wave] = cnt;
   lds_barrier();
@@ -391,13 +393,16 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
     s_small[5] = w0;
     s_small[6] = w0 + w1;
     s_small[7] = w0 + w1 + w2;
-    uint32_t base = gatomic_add(e.slab_cnt + kPoolCounter, total);
-    if (base > e.pool_cap || total > e.pool_cap - base) {
-      // reservations are contiguous, so at most one starts inside the pool and crosses its
-      // end: it marks where the written entries stop
-      if (base <= e.pool_cap) gp(e.slab_cnt)[kPoolCut] = e.pool_cap - base + 1u;
-      gp(e.ovf_list)[gatomic_add(e.slab_cnt + kOvfCounter, 1u)] = (uint32_t)tile;
-      base = kTileOverflow;
+    uint32_t base = 0u;
+    if (total > 0) {
+      base = gatomic_add(e.slab_cnt + kPoolCounter, total);
+      if (base > e.pool_cap || total > e.pool_cap - base) {
+        // reservations are contiguous, so at most one starts inside the pool and crosses its
+        // end: it marks where the written entries stop
+        if (base <= e.pool_cap) gp(e.slab_cnt)[kPoolCut] = e.pool_cap - base + 1u;
+        gp(e.ovf_list)[gatomic_add(e.slab_cnt + kOvfCounter, 1u)] = (uint32_t)tile;
+        base = kTileOverflow;
+      }
     }
     s_small[8] = base;
     gp(e.tile_cnt)[tile] = total;
@@ -410,7 +415,7 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
   for (uint32_t b = s0; b < s1; b += 64) {
     const uint32_t i = b + lane;
     const uint32_t v = i < s1 ? s_tile[i] : 0u;
-    const bool c = i < s1 && v >= T;
+    const bool c = is_cand(i, v);
     const uint64_t m = __ballot(c);
     if (c) {
       if (keep) st_cand(e.pool, run + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)), cell0 + i, v);
@@ -491,10 +496,15 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
 #pragma unroll
     for (int c = 0; c < kListCache; ++c)
       if (threadIdx.x + (uint32_t)c * kBlock < n) vote(cx[c], cr2[c], ck[c]);
-    for (uint32_t h = kListCache * kBlock + threadIdx.x; h < n; h += kBlock) {
-      float x, r2, k;
-      ld_xyz(e.list, beg + h, &x, &r2, &k);
-      vote(x, r2, k);
+    // longer lists: further chunks of kListCache records per thread, each chunk's loads issued
+    // together (one round trip per chunk)
+    for (uint32_t base = kListCache * kBlock; base < n; base += kListCache * kBlock) {  // uniform
+#pragma unroll
+      for (int c = 0; c < kListCache; ++c)
+        ld_xyz(e.list, beg + min(base + threadIdx.x + (uint32_t)c * kBlock, n - 1u), &cx[c], &cr2[c], &ck[c]);
+#pragma unroll
+      for (int c = 0; c < kListCache; ++c)
+        if (base + threadIdx.x + (uint32_t)c * kBlock < n) vote(cx[c], cr2[c], ck[c]);
     }
     lds_barrier();
 
@@ -532,6 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
       if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_small[12], ncand);
       lds_barrier();
       emit_candidates(g, e, tile, cell0, s_tile, L, s_small[12], s_small);
+
     }
     // the LDS tile is all zero again; the next tile's votes start after its first barrier
   }
