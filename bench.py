@@ -194,9 +194,12 @@ def bench_batched(B, torch, synth, workload, n_events, reps, capacity, tune_batc
     return res
 
 
-def bench_served(B, torch, synth, n_pool, n_warm, n_meas, rates, budget_gib, max_batch, n_streams):
+def bench_served(B, torch, synth, n_pool, n_warm, n_meas, rates, budget_gib, max_batch, n_streams,
+                 serve_tuning=None):
     """Served vs plain on workload 3: the same Poisson arrival traces are replayed through the
-    request loop (continuous batching over streams) and through one-at-a-time ht_fill_peaks."""
+    request loop (continuous batching over streams) and through one-at-a-time ht_fill_peaks.
+    serve_tuning (a tuning dict): the launch shape the server is created with (it keeps the shape
+    it was created with); the plain path keeps the grid's current shape."""
     spec = synth.WORKLOADS[3].grid
     pool = [synth.make_event(3, e) for e in range(n_pool)]
     cap = 1 << 17
@@ -222,8 +225,15 @@ def bench_served(B, torch, synth, n_pool, n_warm, n_meas, rates, budget_gib, max
     plain_rate = 200 / (time.perf_counter() - t0)
     res["plain_saturation_events_per_s"] = round(plain_rate, 1)
 
-    with B.Server(spec, budget_gib << 30, peak_capacity=cap, max_hits=40000, max_batch=max_batch,
-                  n_streams=n_streams, queue_depth=1024) as srv:
+    plain_tuning = B.ht_get_tuning(spec)
+    if serve_tuning:
+        B.ht_set_tuning(spec, B.Tuning(**serve_tuning))
+    srv_ctx = B.Server(spec, budget_gib << 30, peak_capacity=cap, max_hits=40000, max_batch=max_batch,
+                       n_streams=n_streams, queue_depth=1024)
+    B.ht_set_tuning(spec, plain_tuning)
+    res["serve_tuning"] = serve_tuning
+    res["plain_tuning"] = plain_tuning.as_dict()
+    with srv_ctx as srv:
         def run_trace(arrivals):
             n = len(arrivals)
             lat, pending, i, done = [], {}, 0, 0
@@ -677,13 +687,13 @@ def main():
         log("batched workload 2")
         line["batched"] = bench_batched(B, torch, synth, 2, 100, 5, 1 << 13, tune_batch=True)
         log("stress workload 4")
-        line["stress"] = bench_batched(B, torch, synth, 4, 16, 3, 1 << 21)
+        line["stress"] = bench_batched(B, torch, synth, 4, 16, 3, 1 << 21, tune_batch=True)
         log("transfer study")
         line["transfers"] = bench_transfers(B, torch, synth, spec)
         log("served workload 3")
         line["served"] = bench_served(B, torch, synth, n_pool=128, n_warm=200, n_meas=2000,
-                                      rates=(0.25, 0.5, 0.9), budget_gib=24, max_batch=8,
-                                      n_streams=2)
+                                      rates=(0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2), budget_gib=24,
+                                      max_batch=8, n_streams=2)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb, _ = cpu_baseline(spec, workload, args.cpu_seconds)

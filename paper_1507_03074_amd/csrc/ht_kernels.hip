@@ -450,6 +450,10 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
 
   const float b_min = g.b_min, inv_db = g.inv_db, nb_f = g.nb_f;
   const uint32_t T = g.threshold;
+  // Workgroups are dealt to the eight XCDs in turn, so consecutive tiles land on different
+  // XCDs and a slab's record list is fetched into every XCD's L2. Giving each XCD one
+  // contiguous range of tiles instead measured 11% slower on the paper grid (eight separate
+  // write streams); the plain order is kept.
   for (int tile = blockIdx.x; tile < g.n_tiles; tile += (int)gridDim.x) {  // uniform
     const int slab = tile / g.tiles_per_slab;
     const int a0 = (tile - slab * g.tiles_per_slab) * ROWS;
