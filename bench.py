@@ -276,6 +276,10 @@ def bench_served(B, torch, synth, n_pool, n_warm, n_meas, rates, budget_gib, max
             arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, n_warm + n_meas))
             lat, t_end = run_trace(arr)
             served = np.array([l for _, l, _ in lat[n_warm:]]) * 1e3
+            tms = [tm for _, _, tm in lat[n_warm:]]
+            parts = {"queue": [t.t_admit - t.t_submit for t in tms],
+                     "admit_to_launch": [t.t_launch - t.t_admit for t in tms],
+                     "launch_to_done": [t.t_done - t.t_launch for t in tms]}
             # plain replay of the same trace: a FIFO single server
             t_base = time.perf_counter()
             plain = []
@@ -292,7 +296,10 @@ def bench_served(B, torch, synth, n_pool, n_warm, n_meas, rates, budget_gib, max
                 "served_p99_ms": round(float(np.percentile(served, 99)), 3),
                 "served_events_per_s": round((n_warm + n_meas) / t_end, 1),
                 "plain_p50_ms": round(float(np.percentile(plain, 50)), 3),
-                "plain_p99_ms": round(float(np.percentile(plain, 99)), 3)})
+                "plain_p99_ms": round(float(np.percentile(plain, 99)), 3),
+                "served_parts_p50_p99_ms": {k: [round(float(np.percentile(v, 50)) * 1e3, 3),
+                                                round(float(np.percentile(v, 99)) * 1e3, 3)]
+                                            for k, v in parts.items()}})
     del acc, dev_pool
     torch.cuda.empty_cache()
     return res

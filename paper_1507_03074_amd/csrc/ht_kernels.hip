@@ -689,27 +689,6 @@ __device__ __forceinline__ void tile_range(const DevGrid& g, int tile, uint32_t*
   *L = (uint32_t)rows * (uint32_t)g.n_b;
 }
 
-// Wave 0 of the block: s_pre = exclusive prefix over the group's tiles of counts[] (tiles whose
-// candidates did not fit the pool count 0 when counts is tile_cnt); s_ovf marks those tiles and
-// s_off holds each tile's chunk offset in the pool.
-__device__ void group_prefix(const EvDesc& e, int t0, int nt, uint32_t* s_pre, uint32_t* s_ovf,
-                             uint32_t* s_off, const uint32_t* counts)
-{
-  // tiles nt..kGroupTiles-1 count zero, so s_pre[nt..kGroupTiles] all equal the group total
-  if (threadIdx.x < kGroupTiles) {
-    const int i = threadIdx.x;
-    uint32_t c = i < nt ? gp(counts)[t0 + i] : 0u;
-    const uint32_t off = i < nt ? gp(e.tile_off)[t0 + i] : 0u;
-    const uint32_t ovf = off == kTileOverflow ? 1u : 0u;
-    s_ovf[i] = ovf;
-    s_off[i] = off;
-    if (ovf && counts == e.tile_cnt) c = 0u;
-    const uint32_t inc = wave_incl_scan(c);
-    s_pre[i + 1] = inc;
-    if (i == 0) s_pre[0] = 0u;
-  }
-}
-
 // Largest t with pre[t] <= f, given pre[0] <= f < pre[kGroupTiles].
 __device__ __forceinline__ int group_tile_of(const uint32_t* pre, uint32_t f)
 {
@@ -783,11 +762,16 @@ __device__ __forceinline__ void count_peak(const DevGrid& g, const EvDesc& e, ui
 __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   EvDesc e = load_ev(ev0, evs);
-  const uint32_t cut = gp(e.slab_cnt)[kPoolCut];
-  const uint32_t n_valid = min(cut ? e.pool_cap + 1u - cut : gp(e.slab_cnt)[kPoolCounter], e.pool_cap);
   const int lane = threadIdx.x & 63, half = lane >> 5, k = lane & 31;
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const uint32_t n_waves = gridDim.x * (kBlock / 64);
+  // this half-wave's first entry is loaded before the entry count is known (an index inside
+  // the pool is always readable), so the count and the entry cost one round trip
+  const uint32_t i_first = 2u * wave + (uint32_t)half;
+  uint2 cv_first = make_uint2(0u, 0u);
+  if (i_first < e.pool_cap) cv_first = ld_cand(e.pool, i_first);
+  const uint32_t cut = gp(e.slab_cnt)[kPoolCut];
+  const uint32_t n_valid = min(cut ? e.pool_cap + 1u - cut : gp(e.slab_cnt)[kPoolCounter], e.pool_cap);
   const uint32_t* acc = e.acc;
   if (n_valid <= 4u * n_waves) {
     for (uint32_t i0 = 2u * wave; i0 < n_valid; i0 += 2u * n_waves) {  // wave-uniform
@@ -796,7 +780,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, con
       uint2 cv = make_uint2(0u, 0u);
       bool beaten = false;
       if (live) {
-        cv = ld_cand(e.pool, i);
+        cv = i == i_first ? cv_first : ld_cand(e.pool, i);
         if (k < 27) beaten = row_beats(g, acc, cv.x, cv.y, k);
       }
       const uint64_t m = __ballot(beaten);
@@ -851,20 +835,38 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
   const int G = blockIdx.x;
   const int t0 = G * g.group_tiles;
   const int nt = min(g.group_tiles, g.n_tiles - t0);
+  // every load that does not depend on another is issued first: the earlier groups' peak
+  // counts (all threads), the group's candidate counts and pool offsets (wave 0) and its peak
+  // counts (wave 1)
   uint32_t part = 0;
   for (int i = threadIdx.x; i < G; i += kBlock) part += gp(e.group_pk)[i];
+  const int ti = (int)(threadIdx.x & 63);
+  uint32_t t_cnt = 0, t_off = 0, t_pk = 0;
+  if (threadIdx.x < 64 && ti < nt) {
+    t_cnt = gp(e.tile_cnt)[t0 + ti];
+    t_off = gp(e.tile_off)[t0 + ti];
+  } else if (threadIdx.x >= 64 && threadIdx.x < 128 && ti < nt) {
+    t_pk = gp(e.tile_pk)[t0 + ti];
+  }
   const uint32_t base32 = block_sum(part, smem);
   const int64_t base = (int64_t)base32;
   if (G == (int)gridDim.x - 1 && threadIdx.x == 0) *gp(e.n_found) = base + gp(e.group_pk)[G];
   if (base >= e.cap) return;  // uniform
-  group_prefix(e, t0, nt, s_pre, s_ovf, s_off, e.tile_cnt);
-  if (threadIdx.x >= 64 && threadIdx.x < 64 + kGroupTiles) {
-    // second wave: prefix of the peak counts of all the group's tiles
-    const int i = threadIdx.x - 64;
-    const uint32_t c = i < nt ? gp(e.tile_pk)[t0 + i] : 0u;
-    const uint32_t inc = wave_incl_scan(c);
-    s_out[i + 1] = inc;
-    if (i == 0) s_out[0] = 0u;
+  static_assert(kGroupTiles == 64, "one wave holds a group's tiles");
+  if (threadIdx.x < 64) {
+    // tiles nt..63 count zero, so s_pre[nt..64] all equal the group's candidate total; tiles
+    // whose candidates did not fit the pool count zero here (they are scanned densely)
+    const uint32_t ovf = t_off == kTileOverflow ? 1u : 0u;
+    s_ovf[ti] = ovf;
+    s_off[ti] = t_off;
+    const uint32_t inc = wave_incl_scan(ovf ? 0u : t_cnt);
+    s_pre[ti + 1] = inc;
+    if (ti == 0) s_pre[0] = 0u;
+  } else if (threadIdx.x < 128) {
+    // prefix of the peak counts of all the group's tiles
+    const uint32_t inc = wave_incl_scan(t_pk);
+    s_out[ti + 1] = inc;
+    if (ti == 0) s_out[0] = 0u;
   }
   lds_barrier();
   const uint32_t total = s_pre[kGroupTiles];
@@ -873,11 +875,13 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
     const uint32_t f = b0 + threadIdx.x;
     bool pk = false;
     int tl = 0;
-    size_t idx = 0;
+    uint2 cv = make_uint2(0u, 0u);
     if (f < total) {
       tl = group_tile_of(s_pre, f);
-      idx = (size_t)s_off[tl] + (f - s_pre[tl]);
+      const size_t idx = (size_t)s_off[tl] + (f - s_pre[tl]);
+      // flag and entry in the same round trip
       pk = gp(e.pk_flag)[idx] != 0;
+      cv = ld_cand(e.pool, idx);
     }
     uint32_t tot;
     const uint32_t pos = run + block_excl_scan(pk ? 1u : 0u, smem, &tot);
@@ -886,10 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
     lds_barrier();
     if (pk) {
       const int64_t o = base + s_out[tl] + (pos - s_first[tl]);
-      if (o < e.cap) {
-        const uint2 cv = ld_cand(e.pool, idx);
-        st_peak(e.out, o, cv.x, cv.y);
-      }
+      if (o < e.cap) st_peak(e.out, o, cv.x, cv.y);
     }
     run += tot;
   }
