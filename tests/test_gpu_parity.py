@@ -687,3 +687,43 @@ def test_batch_autotuner_keeps_results(gpu):
     finally:
         B.ht_set_tuning(CFG0)
     assert B.ht_get_tuning(CFG0).as_dict() == before
+
+
+def test_largest_grid_2pow32_cells(gpu):
+    """The largest grid the layout allows: 8 x 32 x 4096 x 4096 = 2^32 cells (16 GiB of counts),
+    whose last cell index is 2^32 - 1. Fill and peaks bit-exact against the oracle."""
+    import torch
+    B = gpu
+    spec = synth.GridSpec(8, 32, 4096, 4096, threshold=6)
+    assert spec.n_cells == 1 << 32
+    rng = np.random.default_rng(2024)
+    n_tracks = 150
+    ev = synth.make_hits(rng, n_tracks, 200)
+    say("2^32-cell grid:", ev.n, "hits")
+    xd, yd, zd = B.hits_to_device(ev.x, ev.y, ev.z)
+    acc, gc, gv, gn = B.fill_peaks(spec, xd, yd, zd, capacity=1 << 20)
+    torch.cuda.synchronize()
+    say("2^32-cell grid: copying the matrix to the host")
+    gM = B.as_u32(acc)
+    del acc
+    torch.cuda.empty_cache()
+    say("2^32-cell grid: oracle")
+    M, votes, oc, ov, on = oracle_run(spec, ev.x, ev.y, ev.z)
+    say("2^32-cell grid: comparing")
+    assert int(gM.sum(dtype=np.int64)) == votes
+    assert np.array_equal(gM, M)
+    assert gn == on and np.array_equal(gc, oc) and np.array_equal(gv, ov)
+    assert on > 0
+
+
+def test_serve_sector_grid(gpu):
+    """The request loop on the four-sector grid: each result equals the oracle's."""
+    B = gpu
+    spec = sector_grid(CFG0, 4)
+    evs = [synth.make_event(0, 950 + e) for e in range(12)]
+    opts = B.ServeOpts(1 << 30, 256, 2000, 4, 2, 64, 0)
+    say("serve: 12 workload-0 events on four sectors")
+    res = serve_all(B, spec, evs, opts)
+    for ev, (c, v, n, tm) in zip(evs, res):
+        M, votes, oc, ov, on = oracle_run(spec, ev.x, ev.y, ev.z)
+        assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
