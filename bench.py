@@ -713,10 +713,10 @@ def main():
         stream.synchronize()
         lat.append((time.perf_counter() - ts) * 1e3)
     line["plain_latency_ms"] = {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)}
-    line["two_streams"] = bench_two_streams(B, torch, spec, dev_hits, h_out, h_nf, cap, args.steps)
     log("sector variant")
     line["sectors"] = bench_sectors(B, torch, synth, evs, dev_hits, min(args.steps, 300))
     if not args.quick:
+        line["two_streams"] = bench_two_streams(B, torch, spec, dev_hits, h_out, h_nf, cap, args.steps)
         del acc, out
         torch.cuda.empty_cache()
         log("batched workload 2")
