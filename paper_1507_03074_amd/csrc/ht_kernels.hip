@@ -63,11 +63,6 @@ __device__ __forceinline__ const GLOBAL T* gp(const T* p)
 }
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ float4 ld_rec(const float4* p, size_t i)
-{
-  const f32x4 v = ((const GLOBAL f32x4*)p)[i];
-  return make_float4(v.x, v.y, v.z, v.w);
-}
 // (x, r2, k) of a record: three 4-byte loads the compiler merges into one 12-byte load (the
 // unused fourth word is not loaded, so it cannot hold up a register)
 __device__ __forceinline__ void ld_xyz(const float4* p, size_t i, float* x, float* r2, float* k)
@@ -612,9 +607,6 @@ __device__ __forceinline__ void cell_coords(const DevGrid& g, uint32_t c, uint32
   *t = q / np;
 }
 
-struct __attribute__((packed, aligned(4))) U32x3 {
-  uint32_t v0, v1, v2;
-};
 
 // Every neighbour row is fetched before any comparison (no early exit), so a candidate costs one
 // memory round trip: 27 rows of three cells, one 12-byte load each. The window of a row starts
