@@ -510,7 +510,8 @@ def main():
                          "instead of autotuning")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: a 256 MiB copy (the byte-counter reference) "
-                         "three times, then --steps steps untimed; prints one line")
+                         "three times, then --steps steps untimed, then three plain atomic fills; "
+                         "prints one line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -556,8 +557,14 @@ def main():
         for k in range(args.steps):
             step(k)
         torch.cuda.synchronize()
+        # then the plain atomic fill (one global atomicAdd per vote) on the first three events
+        for i in range(3):
+            x, y, z = dev_hits[i % args.events]
+            B.ht_fill(spec, x, y, z, acc, stream, atomic=True)
+        torch.cuda.synchronize()
         print(json.dumps({"counters_run": True, "copy_bytes": copy_bytes, "copies": 3,
-                          "steps": args.steps, "tuning": B.ht_get_tuning(spec).as_dict()}), flush=True)
+                          "steps": args.steps, "atomic_fills": 3,
+                          "tuning": B.ht_get_tuning(spec).as_dict()}), flush=True)
         return
 
     # launch shape from the autotuner (every candidate is gated on bit-exact results)
