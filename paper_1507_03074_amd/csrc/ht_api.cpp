@@ -538,7 +538,7 @@ int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hit
   }
   if (g.lds_fill) {
     StageTimer t("fill", s);
-    if ((rc = check_launch(launch_fill(g, none, d_ev, n_ev, true, s), "fill launch"))) return rc;
+    if ((rc = check_launch(launch_fill(g, none, d_ev, n_ev, true, max_hits, s), "fill launch"))) return rc;
   } else {
     {
       StageTimer t("fill_atomic", s);
@@ -627,7 +627,7 @@ int run_event(const ht_grid* grid, const float* x, const float* y, const float* 
       if ((rc = check_launch(launch_fill_atomic(p.g, ev, nullptr, 1, nh, p.s), "fill launch"))) return rc;
     } else {
       StageTimer t("fill", p.s);
-      if ((rc = check_launch(launch_fill(p.g, ev, nullptr, 1, do_peaks, p.s), "fill launch"))) return rc;
+      if ((rc = check_launch(launch_fill(p.g, ev, nullptr, 1, do_peaks, nh, p.s), "fill launch"))) return rc;
     }
   }
   if (do_peaks) {

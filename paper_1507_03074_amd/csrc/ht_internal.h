@@ -93,7 +93,7 @@ void carve_event_scratch(const DevGrid& g, int64_t n_hits, bool direct, char* ba
 hipError_t launch_prep(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                        int64_t max_hits, bool direct, hipStream_t s);
 hipError_t launch_fill(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
-                       bool emit_candidates, hipStream_t s);
+                       bool emit_candidates, int64_t max_hits, hipStream_t s);
 hipError_t launch_candidates(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                              hipStream_t s);
 hipError_t launch_peaks(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,

@@ -424,13 +424,14 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
 // Fill through an LDS tile of ROWS x n_b counters. The grid holds ceil(n_tiles / fill_tiles)
 // workgroups; workgroup w fills tiles w, w + G, w + 2G, ... (G workgroups), so at any moment the
 // workgroups write one contiguous stretch of the matrix. Per tile: the slab's record list is
-// read (with direct lists the first kListCache records per thread are loaded together with the
-// list length, in one memory round trip; longer lists stream the rest), the votes go to LDS,
-// the tile is written out once, its candidates are pooled, and the LDS tile is left all zero.
+// read (with direct lists the first CACHE records per thread are loaded together with the list
+// length, in one memory round trip; longer lists come in further chunks of CACHE records per
+// thread, each chunk's loads issued together), the votes go to LDS, the tile is written out
+// once, its candidates are pooled, and the LDS tile is left all zero. CACHE is 2 for short
+// lists (few registers, so eight waves fit on each SIMD) and 8 for long ones, where the LDS
+// tile, not the registers, limits how many workgroups fit.
 // ---------------------------------------------------------------------------------------------
-constexpr int kListCache = 2;
-
-template <int ROWS, bool VEC, bool EMIT, bool NT>
+template <int ROWS, bool VEC, bool EMIT, bool NT, int CACHE>
 __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   extern __shared__ uint32_t smem[];
@@ -469,9 +470,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
     }
     // unconditional loads from clamped indices: no branch, so the values land straight in the
     // registers the votes read, and the loads overlap the list-length load
-    float cx[kListCache], cr2[kListCache], ck[kListCache];
+    float cx[CACHE], cr2[CACHE], ck[CACHE];
 #pragma unroll
-    for (int c = 0; c < kListCache; ++c)
+    for (int c = 0; c < CACHE; ++c)
       ld_xyz(e.list, beg + min(threadIdx.x + (uint32_t)c * kBlock, last), &cx[c], &cr2[c], &ck[c]);
     float a2r[ROWS];
 #pragma unroll
@@ -493,16 +494,16 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
       }
     };
 #pragma unroll
-    for (int c = 0; c < kListCache; ++c)
+    for (int c = 0; c < CACHE; ++c)
       if (threadIdx.x + (uint32_t)c * kBlock < n) vote(cx[c], cr2[c], ck[c]);
-    // longer lists: further chunks of kListCache records per thread, each chunk's loads issued
+    // longer lists: further chunks of CACHE records per thread, each chunk's loads issued
     // together (one round trip per chunk)
-    for (uint32_t base = kListCache * kBlock; base < n; base += kListCache * kBlock) {  // uniform
+    for (uint32_t base = CACHE * kBlock; base < n; base += CACHE * kBlock) {  // uniform
 #pragma unroll
-      for (int c = 0; c < kListCache; ++c)
+      for (int c = 0; c < CACHE; ++c)
         ld_xyz(e.list, beg + min(base + threadIdx.x + (uint32_t)c * kBlock, n - 1u), &cx[c], &cr2[c], &ck[c]);
 #pragma unroll
-      for (int c = 0; c < kListCache; ++c)
+      for (int c = 0; c < CACHE; ++c)
         if (base + threadIdx.x + (uint32_t)c * kBlock < n) vote(cx[c], cr2[c], ck[c]);
     }
     lds_barrier();
@@ -998,33 +999,42 @@ __global__ __launch_bounds__(kBlock) void k_debug_hits(DevGrid g, const float* x
   for (int q = 0; q < 4; ++q) slabs[4 * h + q] = q < p.n ? p.slab[q] : -1;
 }
 
-template <int ROWS, bool NT>
-hipError_t launch_fill_rows(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
-                            bool vec, bool emit, size_t lds, hipStream_t s)
+template <int ROWS, bool NT, int CACHE>
+hipError_t launch_fill_cache(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                             bool vec, bool emit, size_t lds, hipStream_t s)
 {
   dim3 grid((g.n_tiles + g.fill_tiles - 1) / g.fill_tiles, n_ev);  // interleaved tiles
   if (vec) {
-    if (emit) hipLaunchKernelGGL((k_fill<ROWS, true, true, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
-    else hipLaunchKernelGGL((k_fill<ROWS, true, false, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
+    if (emit) hipLaunchKernelGGL((k_fill<ROWS, true, true, NT, CACHE>), grid, dim3(kBlock), lds, s, g, ev0, evs);
+    else hipLaunchKernelGGL((k_fill<ROWS, true, false, NT, CACHE>), grid, dim3(kBlock), lds, s, g, ev0, evs);
   } else {
-    if (emit) hipLaunchKernelGGL((k_fill<ROWS, false, true, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
-    else hipLaunchKernelGGL((k_fill<ROWS, false, false, NT>), grid, dim3(kBlock), lds, s, g, ev0, evs);
+    if (emit) hipLaunchKernelGGL((k_fill<ROWS, false, true, NT, CACHE>), grid, dim3(kBlock), lds, s, g, ev0, evs);
+    else hipLaunchKernelGGL((k_fill<ROWS, false, false, NT, CACHE>), grid, dim3(kBlock), lds, s, g, ev0, evs);
   }
   return hipGetLastError();
 }
 
+template <int ROWS, bool NT>
+hipError_t launch_fill_rows(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                            bool vec, bool emit, bool long_lists, size_t lds, hipStream_t s)
+{
+  // long-list variant only where tiles are narrow enough for it to matter (rows <= 8)
+  if (ROWS <= 8 && long_lists) return launch_fill_cache<ROWS, NT, 8>(g, ev0, evs, n_ev, vec, emit, lds, s);
+  return launch_fill_cache<ROWS, NT, 2>(g, ev0, evs, n_ev, vec, emit, lds, s);
+}
+
 template <bool NT>
 hipError_t launch_fill_nt(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev, bool vec,
-                          bool emit, size_t lds, hipStream_t s)
+                          bool emit, bool long_lists, size_t lds, hipStream_t s)
 {
   switch (g.rows) {
-    case 1: return launch_fill_rows<1, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
-    case 2: return launch_fill_rows<2, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
-    case 4: return launch_fill_rows<4, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
-    case 8: return launch_fill_rows<8, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
-    case 16: return launch_fill_rows<16, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
-    case 32: return launch_fill_rows<32, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
-    case 64: return launch_fill_rows<64, NT>(g, ev0, evs, n_ev, vec, emit, lds, s);
+    case 1: return launch_fill_rows<1, NT>(g, ev0, evs, n_ev, vec, emit, long_lists, lds, s);
+    case 2: return launch_fill_rows<2, NT>(g, ev0, evs, n_ev, vec, emit, long_lists, lds, s);
+    case 4: return launch_fill_rows<4, NT>(g, ev0, evs, n_ev, vec, emit, long_lists, lds, s);
+    case 8: return launch_fill_rows<8, NT>(g, ev0, evs, n_ev, vec, emit, long_lists, lds, s);
+    case 16: return launch_fill_rows<16, NT>(g, ev0, evs, n_ev, vec, emit, long_lists, lds, s);
+    case 32: return launch_fill_rows<32, NT>(g, ev0, evs, n_ev, vec, emit, long_lists, lds, s);
+    case 64: return launch_fill_rows<64, NT>(g, ev0, evs, n_ev, vec, emit, long_lists, lds, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1053,13 +1063,16 @@ hipError_t launch_prep(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, i
 }
 
 hipError_t launch_fill(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
-                       bool emit, hipStream_t s)
+                       bool emit, int64_t max_hits, hipStream_t s)
 {
+  // more than two records per thread expected per slab (a hit has at most four cells, about
+  // three on average): load eight per thread per round trip
+  const bool long_lists = max_hits * 3 > (int64_t)2 * kBlock * g.n_slabs;
   // store kind 2: 4-byte stores (the dword path), otherwise 16-byte stores where rows allow
   const bool vec = (g.n_b % 4) == 0 && g.nt_store != 2;
   const size_t lds = fill_lds_bytes(g);
-  if (g.nt_store == 1) return launch_fill_nt<true>(g, ev0, evs, n_ev, vec, emit, lds, s);
-  return launch_fill_nt<false>(g, ev0, evs, n_ev, vec, emit, lds, s);
+  if (g.nt_store == 1) return launch_fill_nt<true>(g, ev0, evs, n_ev, vec, emit, long_lists, lds, s);
+  return launch_fill_nt<false>(g, ev0, evs, n_ev, vec, emit, long_lists, lds, s);
 }
 
 hipError_t launch_candidates(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,

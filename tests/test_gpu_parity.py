@@ -727,3 +727,19 @@ def test_serve_sector_grid(gpu):
     for ev, (c, v, n, tm) in zip(evs, res):
         M, votes, oc, ov, on = oracle_run(spec, ev.x, ev.y, ev.z)
         assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
+
+
+@pytest.mark.parametrize("rows,tpb,nt", [(1, 1, 0), (2, 4, 1), (4, 1, 2), (8, 4, 0), (16, 1, 1), (64, 1, 0)])
+def test_long_slab_lists_bit_exact(gpu, rows, tpb, nt):
+    """Events with about 1000 records per slab: the fill loads its records in chunks of eight
+    per thread (the long-list variant, rows <= 8) or two (wider tiles)."""
+    B = gpu
+    x, y, z = random_hits(77, 22000)
+    M, votes, oc, ov, on = oracle_run(CFG0, x, y, z)
+    say("long lists: rows", rows, "tiles/block", tpb, "store", nt)
+    B.ht_set_tuning(CFG0, rows=rows, tiles_per_block=tpb, nt_store=nt)
+    try:
+        gM, gc, gv, gn = gpu_fused(B, CFG0, x, y, z)
+    finally:
+        B.ht_set_tuning(CFG0)
+    assert_same(CFG0, gM, gc, gv, gn, M, oc, ov, on, "rows %d" % rows)
