@@ -609,10 +609,12 @@ __device__ __forceinline__ void cell_coords(const DevGrid& g, uint32_t c, uint32
 }
 
 
-// Every neighbour row is fetched before any comparison (no early exit), so a candidate costs one
-// memory round trip: 27 rows of three cells, one 12-byte load each. The window of a row starts
-// at min(max(b, 1) - 1, n_b - 3), so it stays inside the row; absent rows (outside theta or A)
-// read the candidate's own row and are masked out.
+// The 27 neighbour rows are taken one theta slice (9 rows of three cells, one 12-byte load each)
+// at a time, its own theta first: the nine loads of a slice are issued together, and a
+// candidate beaten in one slice skips the rest (most candidates are beaten early). The window
+// of a row starts at min(max(b, 1) - 1, n_b - 3), so it stays inside the row; absent rows
+// (outside theta or A, or phi neighbours across sectors) read the candidate's own row and are
+// masked out.
 __device__ bool is_peak(const DevGrid& g, const uint32_t* __restrict__ acc, uint32_t c, uint32_t v)
 {
   const uint32_t nb = (uint32_t)g.n_b, na = (uint32_t)g.n_a, np = (uint32_t)g.n_phi;
@@ -641,36 +643,42 @@ __device__ bool is_peak(const DevGrid& g, const uint32_t* __restrict__ acc, uint
     return !beaten;
   }
   const uint32_t w0 = min(max(b, 1u) - 1u, nb - 3u);
-  uint32_t row[27][3];
-  uint32_t base[27];
-  bool rv[27];
 #pragma unroll
-  for (int k = 0; k < 27; ++k) {
-    const int dt = k / 9 - 1, dp = (k / 3) % 3 - 1, da = k % 3 - 1;
-    const int tt = (int)t + dt, aa = (int)a + da;
-    rv[k] = tt >= 0 && tt < g.n_theta && aa >= 0 && aa < (int)na && !(g.phi_sectors && dp != 0);
-    const uint32_t pp = dp < 0 ? pm : (dp > 0 ? pp1 : p);
-    base[k] = (rv[k] ? (((uint32_t)tt * np + pp) * na + (uint32_t)aa) * nb : c - b) + w0;
-    const GLOBAL uint32_t* rw = gp(acc) + base[k];
-    row[k][0] = rw[0];
-    row[k][1] = rw[1];
-    row[k][2] = rw[2];
-  }
-  bool beaten = false;
+  for (int slice = 0; slice < 3; ++slice) {
+    const int dt = slice == 0 ? 0 : (slice == 1 ? -1 : 1);
+    const int tt = (int)t + dt;
+    if (tt < 0 || tt >= g.n_theta) continue;
+    uint32_t row[9][3];
+    uint32_t base[9];
+    bool rv[9];
 #pragma unroll
-  for (int k = 0; k < 27; ++k) {
-    const bool centre_row = k == 13;
-    const uint32_t* vals = row[k];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const uint32_t bb = w0 + (uint32_t)q;
-      // inside the window; neighbour iff |bb - b| <= 1 and not the candidate itself
-      const bool near = bb + 1u >= b && bb <= b + 1u && !(centre_row && bb == b);
-      const uint32_t n = base[k] + (uint32_t)q;
-      beaten |= rv[k] && near && (vals[q] > v || (vals[q] == v && n < c));
+    for (int k = 0; k < 9; ++k) {
+      const int dp = k / 3 - 1, da = k % 3 - 1;
+      const int aa = (int)a + da;
+      rv[k] = aa >= 0 && aa < (int)na && !(g.phi_sectors && dp != 0);
+      const uint32_t pp = dp < 0 ? pm : (dp > 0 ? pp1 : p);
+      base[k] = (rv[k] ? (((uint32_t)tt * np + pp) * na + (uint32_t)aa) * nb : c - b) + w0;
+      const GLOBAL uint32_t* rw = gp(acc) + base[k];
+      row[k][0] = rw[0];
+      row[k][1] = rw[1];
+      row[k][2] = rw[2];
     }
+    bool beaten = false;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const bool centre_row = dt == 0 && k == 4;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const uint32_t bb = w0 + (uint32_t)q;
+        // inside the window; neighbour iff |bb - b| <= 1 and not the candidate itself
+        const bool near = bb + 1u >= b && bb <= b + 1u && !(centre_row && bb == b);
+        const uint32_t n = base[k] + (uint32_t)q;
+        beaten |= rv[k] && near && (row[k][q] > v || (row[k][q] == v && n < c));
+      }
+    }
+    if (beaten) return false;
   }
-  return !beaten;
+  return true;
 }
 
 __device__ __forceinline__ void tile_range(const DevGrid& g, int tile, uint32_t* cell0, uint32_t* L)
