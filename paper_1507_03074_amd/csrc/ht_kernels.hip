@@ -450,30 +450,43 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
   // XCDs and a slab's record list is fetched into every XCD's L2. Giving each XCD one
   // contiguous range of tiles instead measured 11% slower on the paper grid (eight separate
   // write streams); the plain order is kept.
-  for (int tile = blockIdx.x; tile < g.n_tiles; tile += (int)gridDim.x) {  // uniform
+  //
+  // With long lists and several tiles per workgroup, a workgroup instead fills consecutive
+  // tiles, the A rows of one slab in turn, and keeps the slab's records in registers from one
+  // tile to the next when they all fit (no list load after the first tile).
+  const bool consecutive = CACHE == 8 && g.fill_tiles > 1;  // uniform
+  const int t_begin = consecutive ? (int)blockIdx.x * g.fill_tiles : (int)blockIdx.x;
+  const int t_end = consecutive ? min(t_begin + g.fill_tiles, g.n_tiles) : g.n_tiles;
+  const int t_step = consecutive ? 1 : (int)gridDim.x;
+  int held_slab = -1;  // slab whose whole record list is in registers, or -1
+  size_t beg = 0;
+  uint32_t n = 0;
+  float cx[CACHE], cr2[CACHE], ck[CACHE];
+  for (int tile = t_begin; tile < t_end; tile += t_step) {  // uniform
     const int slab = tile / g.tiles_per_slab;
     const int a0 = (tile - slab * g.tiles_per_slab) * ROWS;
     const int rows = min(ROWS, g.n_a - a0);
     const uint32_t L = (uint32_t)rows * nb;
-    size_t beg;
-    uint32_t n, last;  // records in the list; last readable record (before n is known)
-    if (e.list_cap > 0) {
-      beg = (size_t)slab * (size_t)e.list_cap;
-      n = gp(e.slab_cnt)[slab];
-      last = (uint32_t)e.list_cap - 1u;
-    } else {
-      // the packed list has one record of slack past its end, so beg is always readable
-      const uint32_t o = gp(e.slab_off)[slab];
-      beg = o;
-      n = gp(e.slab_off)[slab + 1] - o;
-      last = n > 0 ? n - 1u : 0u;
-    }
-    // unconditional loads from clamped indices: no branch, so the values land straight in the
-    // registers the votes read, and the loads overlap the list-length load
-    float cx[CACHE], cr2[CACHE], ck[CACHE];
+    if (CACHE != 8 || slab != held_slab) {  // the short-list variant never holds a list
+      uint32_t last;  // last readable record (before n is known)
+      if (e.list_cap > 0) {
+        beg = (size_t)slab * (size_t)e.list_cap;
+        n = gp(e.slab_cnt)[slab];
+        last = (uint32_t)e.list_cap - 1u;
+      } else {
+        // the packed list has one record of slack past its end, so beg is always readable
+        const uint32_t o = gp(e.slab_off)[slab];
+        beg = o;
+        n = gp(e.slab_off)[slab + 1] - o;
+        last = n > 0 ? n - 1u : 0u;
+      }
+      // unconditional loads from clamped indices: no branch, so the values land straight in
+      // the registers the votes read, and the loads overlap the list-length load
 #pragma unroll
-    for (int c = 0; c < CACHE; ++c)
-      ld_xyz(e.list, beg + min(threadIdx.x + (uint32_t)c * kBlock, last), &cx[c], &cr2[c], &ck[c]);
+      for (int c = 0; c < CACHE; ++c)
+        ld_xyz(e.list, beg + min(threadIdx.x + (uint32_t)c * kBlock, last), &cx[c], &cr2[c], &ck[c]);
+      held_slab = (consecutive && n <= (uint32_t)(CACHE * kBlock)) ? slab : -1;
+    }
     float a2r[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) a2r[r] = g.a2[min(a0 + r, g.n_a - 1)];
