@@ -49,7 +49,11 @@
  *     the host, with no copy afterwards. Any other host pointer there is rejected (HT_EINVAL).
  *   - device failures are reported as HT_EDEVICE by the call that observes them.
  *   - the library keeps per-(device, stream) scratch memory; calls on one stream are ordered,
- *     calls on different streams never share scratch.
+ *     calls on different streams never share scratch. Host threads may call concurrently on
+ *     different streams; calls on one stream must come from one host thread at a time (they
+ *     share that stream's scratch and its small host-side state).
+ *   - ht_set_tuning affects calls that start after it returns; it is safe to call from any
+ *     thread.
  */
 #ifndef HT_H_
 #define HT_H_

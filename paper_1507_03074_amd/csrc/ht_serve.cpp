@@ -198,6 +198,9 @@ void loop(ht_server* sv)
       const double tl = now_s();
       for (Request* r : b.reqs) r->t.t_launch = tl;
       int rc = launch(sv, b);
+      // a launch that failed part way may have left copies into the batch's slots in flight:
+      // let them finish before the slots go back to the pool
+      if (rc != HT_OK) (void)hipStreamSynchronize(sv->streams[st]);
       lk.lock();
       if (rc != HT_OK) {
         complete_batch(sv, b, rc);
