@@ -9,13 +9,15 @@
 //                 with LDS-aggregated atomics. Very large events use a counting sort instead:
 //                 k_prep counts, then k_bucket scans the counts in LDS and scatters.
 //   k_fill        one workgroup per (slab, tile of A rows): the slab's records vote into an LDS
-//                 tile (ds_add), then every cell of the tile is written to HBM once with
-//                 coalesced 16-byte stores (so the matrix needs no memset), and the cells >= threshold
-//                 are kept as sorted per-tile candidates (cell, votes)
-//   k_peak_mark   per group of 16-64 tiles: each candidate takes the strict 3^4 test against its
-//                 80 neighbours (a cell below the threshold can never beat a candidate, so only
-//                 candidates need testing); peaks are compacted in order per group
-//   k_peak_write  each group's output offset from the group totals; the ordered peak list
+//                 tile (ds_add), the cells >= threshold go to the event's candidate pool as
+//                 sorted per-tile chunks (cell, votes), then every cell of the tile is written to
+//                 HBM once with coalesced 16-byte stores (so the matrix needs no memset)
+//   k_peak_test   the pooled candidates spread evenly over the workgroups: each takes the strict
+//                 3^4 test against its 80 neighbours (a cell below the threshold can never beat a
+//                 candidate, so only candidates need testing); peaks are counted per tile and
+//                 per group of 16-64 tiles
+//   k_peak_write  per group: its output offset from the earlier groups' totals; the ordered
+//                 peak list
 // ht_peaks on an arbitrary matrix replaces prep and fill with k_cand_scan (one read of it).
 // No kernel synchronises workgroups with each other: on this multi-XCD part an agent-scope
 // release costs an L2 write-back, while a kernel boundary is cheap.
@@ -344,80 +346,135 @@ __global__ __launch_bounds__(kBlock) void k_bucket(DevGrid g, EvDesc ev0, const 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Candidates (cells >= threshold) of one tile, from the tile's counts in LDS: the tile reserves
-// a chunk of the event's candidate pool with one atomic, then each wave writes the candidates
-// of its quarter of the tile in cell order (ballot compaction), so every tile's chunk is sorted
-// by cell index, and clears them in LDS. A tile whose candidates do not fit the pool is
-// recorded as overflowed (searched densely). (Dropping here the cells that lose to a neighbour
-// inside the tile cut the peak test but cost the fill more than it saved.)
-// Called by the whole block; `any` is nonzero iff the tile holds a candidate (a block-uniform
-// hint; the reservation uses this function's own count); s_small: >= 9 words.
+// Candidates (cells >= threshold) of one tile held in LDS. Each wave takes a quarter of the tile
+// (in 16-byte units when VEC, the tile then being a multiple of 4 cells): count_candidates
+// leaves each wave's count in s_small[wave]; after a barrier, emit_candidates reserves the
+// tile's chunk of the event's candidate pool with one atomic and each wave writes the
+// candidates of its quarter in cell order (ballot compaction), so every tile's chunk is sorted
+// by cell index. A tile whose candidates do not fit the pool is recorded as overflowed
+// (searched densely). The LDS tile is left as it was. (Dropping here the cells that lose to a
+// neighbour inside the tile cut the peak test but cost the fill more than it saved.)
+// Both are called by the whole block; s_small: >= 9 words. emit_candidates ends with a barrier
+// when the tile holds candidates, so the caller may then overwrite the tile.
 // ---------------------------------------------------------------------------------------------
+template <bool VEC>
+__device__ __forceinline__ void tile_quarter(uint32_t L, int wave, uint32_t* q0, uint32_t* q1)
+{
+  const uint32_t n = VEC ? L / 4u : L;  // 16-byte units or cells
+  const uint32_t seg = (n + 3u) / 4u;
+  *q0 = min(n, (uint32_t)wave * seg);
+  *q1 = min(n, *q0 + seg);
+}
+
+template <bool VEC>
+__device__ void count_candidates(const uint32_t* s_tile, uint32_t L, uint32_t T, uint32_t* s_small)
+{
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t q0, q1;
+  tile_quarter<VEC>(L, wave, &q0, &q1);
+  uint32_t cnt = 0;  // uniform: sums of ballots
+  if (VEC) {
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(s_tile);
+    const u32x4 zero4 = {0u, 0u, 0u, 0u};
+    for (uint32_t b = q0; b < q1; b += 4 * 64) {
+      u32x4 v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {  // four reads in flight, then the compares
+        const uint32_t i = b + (uint32_t)(k * 64 + lane);
+        v[k] = i < q1 ? s4[i] : zero4;  // T >= 1, so a zero is never a candidate
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        cnt += (uint32_t)(__popcll(__ballot(v[k].x >= T)) + __popcll(__ballot(v[k].y >= T)) +
+                          __popcll(__ballot(v[k].z >= T)) + __popcll(__ballot(v[k].w >= T)));
+    }
+  } else {
+    for (uint32_t b = q0; b < q1; b += 64) {
+      const uint32_t i = b + lane;
+      cnt += (uint32_t)__popcll(__ballot(i < q1 && s_tile[i] >= T));
+    }
+  }
+  if (lane == 0) s_small[wave] = cnt;
+}
+
+template <bool VEC>
 __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uint32_t cell0,
-                                uint32_t* s_tile, uint32_t L, uint32_t any, uint32_t* s_small)
+                                const uint32_t* s_tile, uint32_t L, uint32_t* s_small)
 {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t T = g.threshold;
-  if (threadIdx.x == 0) {
-    // peak counts start at zero; the candidate test (a later launch) adds to them
-    gp(e.tile_pk)[tile] = 0u;
-    if (tile % g.group_tiles == 0) gp(e.group_pk)[tile / g.group_tiles] = 0u;
-  }
-  if (any == 0) {
+  const uint32_t w0 = s_small[0], w1 = s_small[1], w2 = s_small[2];
+  const uint32_t total = w0 + w1 + w2 + s_small[3];
+  if (total == 0) {  // uniform
     if (threadIdx.x == 0) {
+      // peak counts start at zero; the candidate test (a later launch) adds to them
+      gp(e.tile_pk)[tile] = 0u;
+      if (tile % g.group_tiles == 0) gp(e.group_pk)[tile / g.group_tiles] = 0u;
       gp(e.tile_cnt)[tile] = 0u;
       gp(e.tile_off)[tile] = 0u;
     }
     return;
   }
-  const uint32_t seg = (L + 3u) / 4u;
-  const uint32_t s0 = min(L, (uint32_t)wave * seg), s1 = min(L, s0 + seg);
-  auto is_cand = [&](uint32_t i, uint32_t v) { return i < s1 && v >= T; };
-  uint32_t cnt = 0;
-  for (uint32_t b = s0; b < s1; b += 64) {
-    const uint32_t i = b + lane;
-    const uint32_t v = i < s1 ? s_tile[i] : 0u;
-    cnt += (uint32_t)__popcll(__ballot(is_cand(i, v)));
-  }
-  if (lane == 0) s_small[wave] = cnt;
-  lds_barrier();
   if (threadIdx.x == 0) {
-    const uint32_t w0 = s_small[0], w1 = s_small[1], w2 = s_small[2];
-    const uint32_t total = w0 + w1 + w2 + s_small[3];
-    s_small[4] = 0u;
-    s_small[5] = w0;
-    s_small[6] = w0 + w1;
-    s_small[7] = w0 + w1 + w2;
-    uint32_t base = 0u;
-    if (total > 0) {
-      base = gatomic_add(e.slab_cnt + kPoolCounter, total);
-      if (base > e.pool_cap || total > e.pool_cap - base) {
-        // reservations are contiguous, so at most one starts inside the pool and crosses its
-        // end: it marks where the written entries stop
-        if (base <= e.pool_cap) gp(e.slab_cnt)[kPoolCut] = e.pool_cap - base + 1u;
-        gp(e.ovf_list)[gatomic_add(e.slab_cnt + kOvfCounter, 1u)] = (uint32_t)tile;
-        base = kTileOverflow;
-      }
+    uint32_t base = gatomic_add(e.slab_cnt + kPoolCounter, total);
+    if (base > e.pool_cap || total > e.pool_cap - base) {
+      // reservations are contiguous, so at most one starts inside the pool and crosses its
+      // end: it marks where the written entries stop
+      if (base <= e.pool_cap) gp(e.slab_cnt)[kPoolCut] = e.pool_cap - base + 1u;
+      gp(e.ovf_list)[gatomic_add(e.slab_cnt + kOvfCounter, 1u)] = (uint32_t)tile;
+      base = kTileOverflow;
     }
     s_small[8] = base;
     gp(e.tile_cnt)[tile] = total;
     gp(e.tile_off)[tile] = base;
+    gp(e.tile_pk)[tile] = 0u;
+    if (tile % g.group_tiles == 0) gp(e.group_pk)[tile / g.group_tiles] = 0u;
   }
   lds_barrier();
   const uint32_t base = s_small[8];
-  const bool keep = base != kTileOverflow;
-  uint32_t run = base + s_small[4 + wave];
-  for (uint32_t b = s0; b < s1; b += 64) {
-    const uint32_t i = b + lane;
-    const uint32_t v = i < s1 ? s_tile[i] : 0u;
-    const bool c = is_cand(i, v);
-    const uint64_t m = __ballot(c);
-    if (c) {
-      if (keep) st_cand(e.pool, run + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)), cell0 + i, v);
-      s_tile[i] = 0u;  // leaves the LDS tile clear for a workgroup that fills another tile
+  if (base != kTileOverflow) {  // uniform
+    uint32_t q0, q1;
+    tile_quarter<VEC>(L, wave, &q0, &q1);
+    // candidates of the earlier quarters
+    uint32_t run = base + (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
+    const uint64_t below = (1ull << lane) - 1ull;
+    if (VEC) {
+      const u32x4* s4 = reinterpret_cast<const u32x4*>(s_tile);
+      const u32x4 zero4 = {0u, 0u, 0u, 0u};
+      for (uint32_t b = q0; b < q1; b += 2 * 64) {
+        u32x4 v[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t i = b + (uint32_t)(k * 64 + lane);
+          v[k] = i < q1 ? s4[i] : zero4;
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          // cells 4i .. 4i+3 of lane l precede those of lane l+1
+          const uint32_t c = cell0 + 4u * (b + (uint32_t)(k * 64 + lane));
+          const bool c0 = v[k].x >= T, c1 = v[k].y >= T, c2 = v[k].z >= T, c3 = v[k].w >= T;
+          const uint64_t m0 = __ballot(c0), m1 = __ballot(c1), m2 = __ballot(c2), m3 = __ballot(c3);
+          uint32_t r = run + (uint32_t)(__popcll(m0 & below) + __popcll(m1 & below) +
+                                        __popcll(m2 & below) + __popcll(m3 & below));
+          if (c0) st_cand(e.pool, r++, c, v[k].x);
+          if (c1) st_cand(e.pool, r++, c + 1u, v[k].y);
+          if (c2) st_cand(e.pool, r++, c + 2u, v[k].z);
+          if (c3) st_cand(e.pool, r, c + 3u, v[k].w);
+          run += (uint32_t)(__popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3));
+        }
+      }
+    } else {
+      for (uint32_t b = q0; b < q1; b += 64) {
+        const uint32_t i = b + lane;
+        const uint32_t v = i < q1 ? s_tile[i] : 0u;
+        const bool c = v >= T;
+        const uint64_t m = __ballot(c);
+        if (c) st_cand(e.pool, run + (uint32_t)__popcll(m & below), cell0 + i, v);
+        run += (uint32_t)__popcll(m);
+      }
     }
-    run += (uint32_t)__popcll(m);
   }
+  lds_barrier();
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -426,8 +483,8 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
 // workgroups write one contiguous stretch of the matrix. Per tile: the slab's record list is
 // read (with direct lists the first CACHE records per thread are loaded together with the list
 // length, in one memory round trip; longer lists come in further chunks of CACHE records per
-// thread, each chunk's loads issued together), the votes go to LDS, the tile is written out
-// once, its candidates are pooled, and the LDS tile is left all zero. CACHE is 2 for short
+// thread, each chunk's loads issued together), the votes go to LDS, the tile's candidates are
+// pooled, the tile is written out once, and the LDS tile is left all zero. CACHE is 2 for short
 // lists (few registers, so eight waves fit on each SIMD) and 8 for long ones, where the LDS
 // tile, not the registers, limits how many workgroups fit.
 // ---------------------------------------------------------------------------------------------
@@ -490,7 +547,6 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
     float a2r[ROWS];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) a2r[r] = g.a2[min(a0 + r, g.n_a - 1)];
-    if (EMIT && threadIdx.x == 0) s_small[12] = 0u;
     // the LDS tile is zero: set at the start, restored at the end of every tile
     lds_barrier();
     auto vote = [&](float x, float r2, float k) {
@@ -521,41 +577,33 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
     }
     lds_barrier();
 
-    // write the tile out once; without candidates to pool, clear LDS on the way
     const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
+    if (EMIT) {
+      // candidates are pooled before the tile is written, so the wait for the pool reservation
+      // never falls behind this tile's stores (the memory counter a wave waits on counts stores
+      // too); each pass keeps several 16-byte LDS reads in flight per lane
+      count_candidates<VEC>(s_tile, L, T, s_small);
+      lds_barrier();
+      emit_candidates<VEC>(g, e, tile, cell0, s_tile, L, s_small);
+    }
+
+    // write the tile out once, clearing LDS on the way
     GLOBAL uint32_t* dst = gp(e.acc) + cell0;
-    uint32_t ncand = 0;
     if (VEC) {
       GLOBAL u32x4* d4 = reinterpret_cast<GLOBAL u32x4*>(dst);
       for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) {
         const u32x4 v = s4[i];
         if (NT) __builtin_nontemporal_store(v, d4 + i);
         else d4[i] = v;
-        if (EMIT) {
-          // keep only the candidates; emission clears those
-          const u32x4 kept = {v.x >= T ? v.x : 0u, v.y >= T ? v.y : 0u, v.z >= T ? v.z : 0u,
-                              v.w >= T ? v.w : 0u};
-          ncand += (v.x >= T ? 1u : 0u) + (v.y >= T ? 1u : 0u) + (v.z >= T ? 1u : 0u) + (v.w >= T ? 1u : 0u);
-          s4[i] = kept;
-        } else {
-          s4[i] = zero4;
-        }
+        s4[i] = zero4;
       }
     } else {
       for (uint32_t i = threadIdx.x; i < L; i += kBlock) {
         const uint32_t v = s_tile[i];
         if (NT) __builtin_nontemporal_store(v, dst + i);
         else dst[i] = v;
-        if (EMIT) ncand += v >= T ? 1u : 0u;
-        s_tile[i] = (EMIT && v >= T) ? v : 0u;
+        s_tile[i] = 0u;
       }
-    }
-    if (EMIT) {
-      ncand = wave_sum(ncand);
-      if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_small[12], ncand);
-      lds_barrier();
-      emit_candidates(g, e, tile, cell0, s_tile, L, s_small[12], s_small);
-
     }
     // the LDS tile is all zero again; the next tile's votes start after its first barrier
   }
@@ -579,31 +627,19 @@ __global__ __launch_bounds__(kBlock) void k_cand_scan(DevGrid g, EvDesc ev0, con
   const uint32_t Lpad = ((uint32_t)g.rows * nb + 3u) & ~3u;
   uint32_t* s_tile = smem;
   uint32_t* s_small = smem + Lpad;
-  if (threadIdx.x == 0) s_small[12] = 0u;
-  lds_barrier();
   const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
   const GLOBAL uint32_t* src = gp(e.acc) + cell0;
-  const uint32_t T = g.threshold;
-  uint32_t ncand = 0;
   if (VEC) {
     const GLOBAL u32x4* s4 = reinterpret_cast<const GLOBAL u32x4*>(src);
     u32x4* l4 = reinterpret_cast<u32x4*>(s_tile);
-    for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) {
-      const u32x4 v = __builtin_nontemporal_load(s4 + i);
-      l4[i] = v;
-      ncand += (v.x >= T ? 1u : 0u) + (v.y >= T ? 1u : 0u) + (v.z >= T ? 1u : 0u) + (v.w >= T ? 1u : 0u);
-    }
+    for (uint32_t i = threadIdx.x; i < L / 4; i += kBlock) l4[i] = __builtin_nontemporal_load(s4 + i);
   } else {
-    for (uint32_t i = threadIdx.x; i < L; i += kBlock) {
-      const uint32_t v = src[i];
-      s_tile[i] = v;
-      ncand += v >= T ? 1u : 0u;
-    }
+    for (uint32_t i = threadIdx.x; i < L; i += kBlock) s_tile[i] = src[i];
   }
-  ncand = wave_sum(ncand);
-  if ((threadIdx.x & 63) == 0 && ncand) atomicAdd(&s_small[12], ncand);
   lds_barrier();
-  emit_candidates(g, e, tile, cell0, s_tile, L, s_small[12], s_small);
+  count_candidates<VEC>(s_tile, L, g.threshold, s_small);
+  lds_barrier();
+  emit_candidates<VEC>(g, e, tile, cell0, s_tile, L, s_small);
 }
 
 // ---------------------------------------------------------------------------------------------
