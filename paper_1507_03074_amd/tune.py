@@ -41,6 +41,23 @@ def candidates(spec):
         yield B.Tuning(r, 0, 0, nt, tpb)
 
 
+def _refine(results, key, time_one, top=3, rounds=5):
+    """Re-time the `top` fastest bit-exact shapes in interleaved rounds and store the median
+    under `key`: one pass per shape is at the mercy of clock and cache drift, and the first
+    sweep only ranks the shapes roughly."""
+    ok = sorted((r for r in results if r["bit_exact"]), key=lambda r: r[key])[:top]
+    if len(ok) < 2:
+        return
+    times = {id(r): [] for r in ok}
+    for _ in range(rounds):
+        for r in ok:
+            times[id(r)].append(time_one(r["tuning"]))
+    for r in ok:
+        r["first_" + key] = r[key]
+        r[key] = float(np.median(times[id(r)]))
+        r["rounds"] = rounds
+
+
 def _run(spec, hits, acc, out, nf, cap, reps):
     import torch
     for x, y, z in hits:
@@ -99,6 +116,12 @@ def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool 
         for gt in (16, 32, 64):
             if gt != f["group_tiles"]:
                 trial(B.Tuning(f["rows"], gt, 0, f["nt_store"], f["tiles_per_block"]))
+
+    def time_one(tuning):
+        B.ht_set_tuning(spec, B.Tuning(**tuning))
+        return _run(spec, hits, acc, out, nf, capacity, 3 * reps) * 1e6
+
+    _refine(results, "us_per_event", time_one)
     B.ht_set_tuning(spec)
     ok = [r for r in results if r["bit_exact"]]
     best = min(ok, key=lambda r: r["us_per_event"]) if ok else None
@@ -177,6 +200,12 @@ def autotune_batch(spec, events, reps: int = 3, capacity: int = 1 << 13, apply: 
         for gt in (16, 32, 64):
             if gt != f["group_tiles"]:
                 trial(B.Tuning(f["rows"], gt, 0, f["nt_store"], f["tiles_per_block"]))
+
+    def time_one(tuning):
+        B.ht_set_tuning(spec, B.Tuning(**tuning))
+        return timed() * 1e3
+
+    _refine(results, "ms_per_batch", time_one, rounds=3)
     B.ht_set_tuning(spec)
     ok = [r for r in results if r["bit_exact"]]
     best = min(ok, key=lambda r: r["ms_per_batch"]) if ok else None
