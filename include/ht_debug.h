@@ -23,6 +23,14 @@ extern "C" {
 int ht_debug_hit_values(const ht_grid* grid, const float* x, const float* y, const float* z,
                         int64_t n_hits, int32_t* info, float* vals, int32_t* slabs, void* stream);
 
+/* ht_debug_unary: the two correctly rounded operations of the per-hit values (bin rule O2),
+ * computed by the same device functions the preparation uses: root[i] = sqrtf(v[i]) and
+ * inv2[i] = 1.0f / (v[i] + v[i]), each one IEEE binary32 operation rounded to nearest even (v + v
+ * is exact below overflow). Meant for checking them against the host over every binary32 input.
+ * v, root, inv2: float[n], device memory or mapped pinned host memory, caller-owned.
+ * Asynchronous on stream. Errors: HT_EINVAL (n < 0, NULL or unusable pointers), HT_EDEVICE. */
+int ht_debug_unary(const float* v, float* root, float* inv2, int64_t n, void* stream);
+
 /* ht_debug_pointer_kind: how the library classifies a pointer given as a peak output, from the
  * HIP runtime's attributes (host only, no device work): 0 = refused (not usable by a kernel,
  * e.g. unregistered host memory), 1 = device memory, 2 = pinned host memory mapped into the

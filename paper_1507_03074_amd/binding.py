@@ -87,7 +87,7 @@ class Timing(ctypes.Structure):
 #: every symbol the public headers declare
 EXPORTS = ["ht_set_tuning", "ht_get_tuning", "ht_tables", "ht_fill", "ht_peaks", "ht_fill_peaks", "ht_fill_peaks_batch",
            "ht_serve_create", "ht_serve_submit", "ht_serve_poll", "ht_serve_destroy",
-           "ht_last_error", "ht_debug_hit_values", "ht_fill_atomic", "ht_tiling",
+           "ht_last_error", "ht_debug_hit_values", "ht_debug_unary", "ht_fill_atomic", "ht_tiling",
            "ht_profile_enable", "ht_profile_read", "ht_bench_hbm_write", "ht_bench_hbm_read",
            "ht_bench_copy", "ht_bench_atomic_rand", "ht_bench_lds_atomic", "ht_readout",
            "ht_debug_pointer_kind"]
@@ -120,6 +120,7 @@ def lib():
         "ht_fill_peaks_batch": ([gp, ctypes.POINTER(Event), i32, vp, vp, vp, vp, vp, vp, vp],
                                 ctypes.c_int),
         "ht_debug_hit_values": ([gp, vp, vp, vp, i64, vp, vp, vp, vp], ctypes.c_int),
+        "ht_debug_unary": ([vp, vp, vp, i64, vp], ctypes.c_int),
         "ht_readout": ([gp, vp, vp, i64, vp, vp], ctypes.c_int),
         "ht_debug_pointer_kind": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
         "ht_serve_create": ([gp, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)], ctypes.c_int),
@@ -311,6 +312,15 @@ def ht_debug_hit_values(spec, x, y, z, stream=None):
     check(lib().ht_debug_hit_values(ctypes.byref(g), _ptr(x), _ptr(y), _ptr(z), n, _ptr(info),
                                     _ptr(vals), _ptr(slabs), _stream(stream)))
     return info, vals, slabs
+
+
+def ht_debug_unary(v, root, inv2, stream=None):
+    """root = sqrt(v) and inv2 = 1 / (v + v) on the device (float32 tensors of one size)."""
+    _need_cuda(v, root, inv2)
+    n = v.numel()
+    if root.numel() != n or inv2.numel() != n:
+        raise ValueError("v, root and inv2 must have the same size")
+    check(lib().ht_debug_unary(_ptr(v), _ptr(root), _ptr(inv2), n, _stream(stream)))
 
 
 def ht_profile_enable(mode):

@@ -18,6 +18,7 @@
 namespace ht {
 hipError_t launch_debug_hits(const DevGrid& g, const float* x, const float* y, const float* z,
                              int64_t n, int32_t* info, float* vals, int32_t* slabs, hipStream_t s);
+hipError_t launch_debug_unary(const float* v, float* root, float* inv2, int64_t n, hipStream_t s);
 
 thread_local std::string g_err;
 
@@ -882,6 +883,16 @@ int ht_debug_hit_values(const ht_grid* grid, const float* x, const float* y, con
   int rc = prepare(grid, stream, &p);
   if (rc) return rc;
   return check_launch(launch_debug_hits(p.g, x, y, z, n_hits, info, vals, slabs, p.s), "debug launch");
+}
+
+int ht_debug_unary(const float* v, float* root, float* inv2, int64_t n, void* stream)
+{
+  if (n < 0) return fail(HT_EINVAL, "n < 0");
+  if (n == 0) return HT_OK;
+  if (!v || !root || !inv2) return fail(HT_EINVAL, "NULL pointer");
+  if (pointer_kind(v) == 0 || pointer_kind(root) == 0 || pointer_kind(inv2) == 0)
+    return fail(HT_EINVAL, "an array is not device-accessible memory");
+  return check_launch(launch_debug_unary(v, root, inv2, n, (hipStream_t)stream), "debug launch");
 }
 
 int ht_profile_enable(int mode)

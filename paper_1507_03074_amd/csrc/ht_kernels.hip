@@ -168,6 +168,16 @@ __device__ __forceinline__ int half_plane(float c, float s, float vx, float vy)
   return d >= 0.0f ? 1 : 0;
 }
 
+// The two correctly rounded operations of the per-hit values: r = sqrt(r2) and k = 1/(2y)
+// (2y is exact). Shared by the preparation and by ht_debug_unary, which checks them against
+// the host over every binary32 input.
+__device__ __forceinline__ float hit_root(float r2) { return sqrtf(r2); }
+__device__ __forceinline__ float hit_inv2(float y)
+{
+  float ty = y + y;
+  return 1.0f / ty;
+}
+
 struct HitPrep {
   int n;  // number of (theta, phi) cells, 0 when the hit votes nothing
   int slab[4];
@@ -187,9 +197,8 @@ __device__ HitPrep prep_hit(const DevGrid& g, float x, float y, float z)
   float yy = y * y;
   float r2 = xx + yy;
   if (!(r2 > 0.0f) || isinf(r2)) return h;
-  float r = sqrtf(r2);
-  float ty = y + y;
-  float k = 1.0f / ty;
+  float r = hit_root(r2);
+  float k = hit_inv2(y);
   int s_phi;
   if (y > 0.0f) {
     s_phi = 0;
@@ -1056,6 +1065,17 @@ __global__ __launch_bounds__(kBlock) void k_debug_hits(DevGrid g, const float* x
   for (int q = 0; q < 4; ++q) slabs[4 * h + q] = q < p.n ? p.slab[q] : -1;
 }
 
+__global__ __launch_bounds__(kBlock) void k_debug_unary(const float* v, float* root, float* inv2,
+                                                        int64_t n)
+{
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const float a = v[i];
+    root[i] = hit_root(a);
+    inv2[i] = hit_inv2(a);
+  }
+}
+
 template <int ROWS, bool NT, int CACHE>
 hipError_t launch_fill_cache(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                              bool vec, bool emit, size_t lds, hipStream_t s)
@@ -1175,6 +1195,15 @@ hipError_t launch_debug_hits(const DevGrid& g, const float* x, const float* y, c
   if (n > 0)
     hipLaunchKernelGGL(k_debug_hits, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        g, x, y, z, n, info, vals, slabs);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_unary(const float* v, float* root, float* inv2, int64_t n, hipStream_t s)
+{
+  if (n > 0) {
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 16384);
+    hipLaunchKernelGGL(k_debug_unary, dim3((unsigned)blocks), dim3(kBlock), 0, s, v, root, inv2, n);
+  }
   return hipGetLastError();
 }
 

@@ -158,6 +158,16 @@ def test_profile_modes_validated_on_host(lib):
     assert lib.ht_profile_enable(0) == 0
 
 
+def test_debug_unary_validated_on_host(lib):
+    """Checked before any device work: a negative size or a NULL array is HT_EINVAL; an empty
+    call does nothing."""
+    dummy = ctypes.c_void_p(256)
+    assert lib.ht_debug_unary(dummy, dummy, dummy, -1, None) == B.HT_EINVAL
+    assert lib.ht_debug_unary(None, None, None, 0, None) == 0
+    assert lib.ht_debug_unary(None, dummy, dummy, 4, None) == B.HT_EINVAL
+    assert lib.ht_debug_unary(dummy, dummy, None, 4, None) == B.HT_EINVAL
+
+
 def test_sector_grids_validated_on_host(lib):
     """phi_sectors is 0 or 1; with sectors n_phi may be 1 or 2; the tables do not depend on it."""
     from oracle import oracle
