@@ -29,8 +29,10 @@ def disasm(tmp_path_factory):
     if not all(t and os.path.exists(t) for t in tools):
         pytest.skip("objcopy / ROCm LLVM tools not available")
     d = tmp_path_factory.mktemp("isa")
-    fat, co = str(d / "fatbin"), str(d / "gfx950.co")
-    subprocess.check_call([tools[0], "--dump-section", ".hip_fatbin=" + fat, B.LIB_PATH])
+    fat, co, scratch = str(d / "fatbin"), str(d / "gfx950.co"), str(d / "copy.so")
+    # with no output file objcopy would rewrite the library in place, under this process's
+    # own mapping of it: the rewritten copy goes to the scratch file instead
+    subprocess.check_call([tools[0], "--dump-section", ".hip_fatbin=" + fat, B.LIB_PATH, scratch])
     subprocess.check_call([tools[1], "--unbundle", "--type=o",
                            "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--input=" + fat,
                            "--output=" + co])
