@@ -185,14 +185,18 @@ struct HitPrep {
   float x, r2, r, k;
 };
 
-__device__ HitPrep prep_hit(const DevGrid& g, float x, float y, float z)
+// phi_cs, th_cs: the boundary tables (g.phi_cs, g.th_cs or a copy of them in LDS).
+__device__ HitPrep prep_hit(const DevGrid& g, const float* phi_cs, const float* th_cs, float x,
+                            float y, float z)
 {
   HitPrep h;
   h.n = 0;
   h.s_theta = h.s_phi = 0;
   h.x = x;
   h.r2 = h.r = h.k = 0.0f;
-  if (!(isfinite(x) && isfinite(y) && isfinite(z)) || y == 0.0f) return h;
+  // one test of all three coordinates (no short cut), so the load of z is not held back until
+  // x and y have been checked
+  if (!(isfinite(x) & isfinite(y) & isfinite(z)) | (y == 0.0f)) return h;
   float xx = x * x;
   float yy = y * y;
   float r2 = xx + yy;
@@ -202,14 +206,14 @@ __device__ HitPrep prep_hit(const DevGrid& g, float x, float y, float z)
   int s_phi;
   if (y > 0.0f) {
     s_phi = 0;
-    for (int m = 1; m < g.n_phi; ++m) s_phi += half_plane(g.phi_cs[2 * m], g.phi_cs[2 * m + 1], x, y);
+    for (int m = 1; m < g.n_phi; ++m) s_phi += half_plane(phi_cs[2 * m], phi_cs[2 * m + 1], x, y);
   } else {
     s_phi = g.n_phi;
     for (int m = g.n_phi + 1; m < 2 * g.n_phi; ++m)
-      s_phi += half_plane(g.phi_cs[2 * m], g.phi_cs[2 * m + 1], x, y);
+      s_phi += half_plane(phi_cs[2 * m], phi_cs[2 * m + 1], x, y);
   }
   int s_th = 0;
-  for (int m = 1; m < 2 * g.n_theta; ++m) s_th += half_plane(g.th_cs[2 * m], g.th_cs[2 * m + 1], z, r);
+  for (int m = 1; m < 2 * g.n_theta; ++m) s_th += half_plane(th_cs[2 * m], th_cs[2 * m + 1], z, r);
   const int p0 = s_phi >> 1;
   const int p1 = (s_phi & 1) ? (p0 + 1 == g.n_phi ? 0 : p0 + 1) : (p0 == 0 ? g.n_phi - 1 : p0 - 1);
   const int t0 = s_th >> 1;
@@ -240,27 +244,56 @@ __device__ HitPrep prep_hit(const DevGrid& g, float x, float y, float z)
   return h;
 }
 
+// The boundary tables copied into LDS (dynamic shared memory): the sector counts then read
+// them at LDS latency instead of one scalar load after another. The caller's next barrier makes
+// the copy visible. Without LDS_TABLES (grids whose tables exceed kLdsTableBytes) the tables are
+// read from global memory.
+constexpr size_t kLdsTableBytes = 16384;
+
+template <bool LDS_TABLES>
+__device__ __forceinline__ void tables_to_lds(const DevGrid& g, float* s_tab, const float** tab_phi,
+                                              const float** tab_th)
+{
+  if (!LDS_TABLES) {
+    *tab_phi = g.phi_cs;
+    *tab_th = g.th_cs;
+    return;
+  }
+  const int n_phi = 4 * g.n_phi, n_th = 2 * (2 * g.n_theta + 1);
+  for (int i = threadIdx.x; i < n_phi + n_th; i += kBlock)
+    s_tab[i] = i < n_phi ? gp(g.phi_cs)[i] : gp(g.th_cs)[i - n_phi];
+  *tab_phi = s_tab;
+  *tab_th = s_tab + n_phi;
+}
+
 // Direct lists: counts per slab in LDS per workgroup, one global atomic per (workgroup, slab)
 // reserves the workgroup's range of each slab's fixed-capacity list, then the records are
 // written there. slab_cnt is zero on entry and ends holding the list lengths; workgroup 0 clears
 // the other counter array for the next call.
+template <bool LDS_TABLES>
 __global__ __launch_bounds__(kBlock) void k_prep_direct(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   __shared__ uint32_t lcnt[kMaxSlabs];
+  extern __shared__ float s_tab[];
   EvDesc e = load_ev(ev0, evs);
   // clear all of the other array: an earlier call on a grid with more slabs may have used
   // entries past this grid's n_slabs
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < kCounterWords; i += kBlock) gp(e.slab_cnt_next)[i] = 0u;
   if ((int64_t)blockIdx.x * kBlock >= e.n_hits) return;  // uniform: whole block idle
+  const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // the hit's coordinates are loaded first, so their round trip overlaps the table copy
+  const int64_t hc = min(h, e.n_hits - 1);
+  const float hx = gp(e.x)[hc], hy = gp(e.y)[hc], hz = gp(e.z)[hc];
+  const float *tab_phi, *tab_th;
+  tables_to_lds<LDS_TABLES>(g, s_tab, &tab_phi, &tab_th);
   for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) lcnt[i] = 0u;
   lds_barrier();
-  const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   HitPrep p;
   p.n = 0;
   uint32_t local[4] = {0u, 0u, 0u, 0u};
   if (h < e.n_hits) {
-    p = prep_hit(g, gp(e.x)[h], gp(e.y)[h], gp(e.z)[h]);
+    p = prep_hit(g, tab_phi, tab_th, hx, hy, hz);
     // constant indices keep p.slab and local in registers (a runtime index would put them in
     // scratch memory)
 #pragma unroll
@@ -283,23 +316,29 @@ __global__ __launch_bounds__(kBlock) void k_prep_direct(DevGrid g, EvDesc ev0, c
 
 // Counting sort, first pass: counts per slab (LDS, then one global atomic per workgroup and
 // slab) and each record's position within its slab. Workgroup 0 clears the other counter array.
+template <bool LDS_TABLES>
 __global__ __launch_bounds__(kBlock) void k_prep(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   __shared__ uint32_t lcnt[kMaxSlabs];
+  extern __shared__ float s_tab[];
   EvDesc e = load_ev(ev0, evs);
   // clear all of the other array: an earlier call on a grid with more slabs may have used
   // entries past this grid's n_slabs
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < kCounterWords; i += kBlock) e.slab_cnt_next[i] = 0u;
   if ((int64_t)blockIdx.x * kBlock >= e.n_hits) return;  // uniform: whole block idle
+  const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t hc = min(h, e.n_hits - 1);
+  const float hx = gp(e.x)[hc], hy = gp(e.y)[hc], hz = gp(e.z)[hc];
+  const float *tab_phi, *tab_th;
+  tables_to_lds<LDS_TABLES>(g, s_tab, &tab_phi, &tab_th);
   for (int i = threadIdx.x; i < g.n_slabs; i += kBlock) lcnt[i] = 0u;
   lds_barrier();
-  const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   HitPrep p;
   p.n = 0;
   uint32_t local[4] = {0u, 0u, 0u, 0u};
   if (h < e.n_hits) {
-    p = prep_hit(g, e.x[h], e.y[h], e.z[h]);
+    p = prep_hit(g, tab_phi, tab_th, hx, hy, hz);
     e.hit_rec[h] = make_float4(p.x, p.r2, p.k, 0.0f);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1054,7 +1093,7 @@ __global__ __launch_bounds__(kBlock) void k_debug_hits(DevGrid g, const float* x
 {
   const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (h >= n) return;
-  HitPrep p = prep_hit(g, x[h], y[h], z[h]);
+  HitPrep p = prep_hit(g, g.phi_cs, g.th_cs, x[h], y[h], z[h]);
   info[4 * h + 0] = p.n > 0;
   info[4 * h + 1] = p.s_theta;
   info[4 * h + 2] = p.s_phi;
@@ -1130,11 +1169,16 @@ hipError_t launch_prep(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, i
                        int64_t max_hits, bool direct, hipStream_t s)
 {
   const unsigned blocks = (unsigned)std::max<int64_t>(1, (max_hits + kBlock - 1) / kBlock);
+  // the boundary tables: 4 n_phi + 2 (2 n_theta + 1) floats (about 300 B for the paper grid)
+  const size_t tab = (size_t)(4 * g.n_phi + 2 * (2 * g.n_theta + 1)) * sizeof(float);
+  const bool lds = tab <= kLdsTableBytes;
   if (direct) {
-    hipLaunchKernelGGL(k_prep_direct, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
+    if (lds) hipLaunchKernelGGL(k_prep_direct<true>, dim3(blocks, n_ev), dim3(kBlock), tab, s, g, ev0, evs);
+    else hipLaunchKernelGGL(k_prep_direct<false>, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_prep, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
+  if (lds) hipLaunchKernelGGL(k_prep<true>, dim3(blocks, n_ev), dim3(kBlock), tab, s, g, ev0, evs);
+  else hipLaunchKernelGGL(k_prep<false>, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
   hipLaunchKernelGGL(k_bucket, dim3(blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
   return hipGetLastError();
 }
