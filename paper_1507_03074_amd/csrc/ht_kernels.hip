@@ -110,22 +110,31 @@ __device__ __forceinline__ void lds_barrier()
 // ---------------------------------------------------------------------------------------------
 // Wave / block scans (wave64)
 // ---------------------------------------------------------------------------------------------
+// Inclusive scan over a wave64 with DPP moves, which stay in the VALU (no LDS round trips):
+// Hillis-Steele shifts inside each row of 16 lanes, then the last lane of row 0 is added to
+// row 1 and row 3, and that of row 1 (lane 31) to rows 2 and 3. A lane whose source lies
+// outside its row is masked off and adds 0. Every lane of the wave must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_add(uint32_t v)
+{
+  return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-  const int lane = __lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
+  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
+// Sum over a wave64 (every lane active); the result is uniform.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
 }
 
 // Exclusive scan over the block (blockDim a multiple of 64, at most 1024). smem: >= 17 words.
@@ -936,8 +945,6 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
   // every load that does not depend on another is issued first: the earlier groups' peak
   // counts (all threads), the group's candidate counts and pool offsets (wave 0) and its peak
   // counts (wave 1)
-  uint32_t part = 0;
-  for (int i = threadIdx.x; i < G; i += kBlock) part += gp(e.group_pk)[i];
   const int ti = (int)(threadIdx.x & 63);
   uint32_t t_cnt = 0, t_off = 0, t_pk = 0;
   if (threadIdx.x < 64 && ti < nt) {
@@ -945,6 +952,17 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
     t_off = gp(e.tile_off)[t0 + ti];
   } else if (threadIdx.x >= 64 && threadIdx.x < 128 && ti < nt) {
     t_pk = gp(e.tile_pk)[t0 + ti];
+  }
+  // four loads in flight per thread and round (groups past G read as zero)
+  uint32_t part = 0;
+  for (int i0 = 0; i0 < G; i0 += 4 * kBlock) {  // uniform
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * kBlock + (int)threadIdx.x;
+      w[k] = i < G ? gp(e.group_pk)[i] : 0u;
+    }
+    part += w[0] + w[1] + w[2] + w[3];
   }
   const uint32_t base32 = block_sum(part, smem);
   const int64_t base = (int64_t)base32;
