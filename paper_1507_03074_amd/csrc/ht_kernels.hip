@@ -38,9 +38,19 @@ constexpr int kBlock = 256;
 static_assert(kBlock == 256, "candidate emission splits a tile over four wave64s");
 constexpr int kGroupTiles = 64;  // largest group of tiles per peak workgroup (g.group_tiles)
 
+// A launch's event descriptor: the kernel argument for one event, else evs[blockIdx.y]. The
+// descriptor array is read through the constant address space: both sources are then
+// scalar-loaded (a generic pointer chosen between the two would make every field a vector
+// memory load, one more round trip before each workgroup's first real load).
+#define CONSTANT __attribute__((address_space(4)))
 __device__ __forceinline__ EvDesc load_ev(const EvDesc& ev0, const EvDesc* evs)
 {
-  return evs ? evs[blockIdx.y] : ev0;
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (evs) return ((const CONSTANT EvDesc*)evs)[blockIdx.y];
+#else
+  if (evs) return evs[blockIdx.y];  // the host pass only parses device functions
+#endif
+  return ev0;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -877,8 +887,11 @@ __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, con
   const uint32_t i_first = 2u * wave + (uint32_t)half;
   uint2 cv_first = make_uint2(0u, 0u);
   if (i_first < e.pool_cap) cv_first = ld_cand(e.pool, i_first);
+  // the three counters load together (none waits for another)
   const uint32_t cut = gp(e.slab_cnt)[kPoolCut];
-  const uint32_t n_valid = min(cut ? e.pool_cap + 1u - cut : gp(e.slab_cnt)[kPoolCounter], e.pool_cap);
+  const uint32_t reserved = gp(e.slab_cnt)[kPoolCounter];
+  const uint32_t n_ovf = gp(e.slab_cnt)[kOvfCounter];
+  const uint32_t n_valid = min(cut ? e.pool_cap + 1u - cut : reserved, e.pool_cap);
   const uint32_t* acc = e.acc;
   if (n_valid <= 4u * n_waves) {
     for (uint32_t i0 = 2u * wave; i0 < n_valid; i0 += 2u * n_waves) {  // wave-uniform
@@ -907,7 +920,6 @@ __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, con
       if (pk) count_peak(g, e, cv.x);
     }
   }
-  const uint32_t n_ovf = gp(e.slab_cnt)[kOvfCounter];
   for (uint32_t j = wave; j < n_ovf; j += n_waves) {
     const int tile = (int)gp(e.ovf_list)[j];
     uint32_t cell0, L;
