@@ -37,7 +37,7 @@ def candidates(spec):
     g = B.make_grid(spec)
     rows = [r for r in (1, 2, 4, 8, 16, 32, 64) if r * g.n_b * 4 <= 57344 and r <= max(1, g.n_a)]
     rows = rows[-3:] if len(rows) > 3 else rows
-    for r, tpb, nt in itertools.product(rows, (1, 4, 8), (0, 1, 2)):
+    for r, tpb, nt in itertools.product(rows, (1, 2, 4, 8), (0, 1, 2)):
         yield B.Tuning(r, 0, 0, nt, tpb)
 
 
