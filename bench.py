@@ -514,8 +514,9 @@ def main():
                          "prints one line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(events shard across GPUs with no collective; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path. Events are "
+              "independent, so several GPUs would each run their own events (or request loop) "
+              "with no collective between them.", file=sys.stderr)
         sys.exit(2)
 
     import torch
