@@ -99,9 +99,17 @@ __device__ __forceinline__ void st_cand(uint2* p, size_t i, uint32_t cell, uint3
   const u32x2 w = {cell, votes};
   ((GLOBAL u32x2*)p)[i] = w;
 }
-// an output peak: two 4-byte stores (the caller's array need only be 4-byte aligned)
-__device__ __forceinline__ void st_peak(ht_peak* p, int64_t i, uint32_t cell, uint32_t votes)
+// an output peak: one 8-byte store when the caller's array is 8-byte aligned (a wave's peaks
+// then go out as one contiguous run, which matters when the array is host memory mapped into
+// the GPU: every store becomes a bus write), else two 4-byte stores (the array need only be
+// 4-byte aligned). a8 is uniform.
+__device__ __forceinline__ void st_peak(ht_peak* p, int64_t i, uint32_t cell, uint32_t votes, bool a8)
 {
+  if (a8) {
+    const u32x2 w = {cell, votes};
+    ((GLOBAL u32x2*)p)[i] = w;
+    return;
+  }
   GLOBAL uint32_t* q = (GLOBAL uint32_t*)p + 2 * i;
   q[0] = cell;
   q[1] = votes;
@@ -953,6 +961,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
   EvDesc e = load_ev(ev0, evs);
   const int G = blockIdx.x;
   const int t0 = G * g.group_tiles;
+  const bool a8 = ((uintptr_t)e.out & 7u) == 0;
   const int nt = min(g.group_tiles, g.n_tiles - t0);
   // every load that does not depend on another is issued first: the earlier groups' peak
   // counts (all threads), the group's candidate counts and pool offsets (wave 0) and its peak
@@ -1018,7 +1027,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
     lds_barrier();
     if (pk) {
       const int64_t o = base + s_out[tl] + (pos - s_first[tl]);
-      if (o < e.cap) st_peak(e.out, o, cv.x, cv.y);
+      if (o < e.cap) st_peak(e.out, o, cv.x, cv.y, a8);
     }
     run += tot;
   }
@@ -1040,7 +1049,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
       }
       const uint64_t m = __ballot(pk);
       const int64_t o = base + s_out[tl] + r + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-      if (pk && o < e.cap) st_peak(e.out, o, c, v);
+      if (pk && o < e.cap) st_peak(e.out, o, c, v, a8);
       r += (uint32_t)__popcll(m);
     }
   }

@@ -542,6 +542,36 @@ def test_peaks_written_to_pinned_host_memory(gpu):
         assert np.array_equal(got[:, 0], oc) and np.array_equal(got[:, 1], ov)
 
 
+def test_peaks_into_4_byte_aligned_output(gpu):
+    """Peak lists that start 4 bytes past an 8-byte boundary (in device memory and in pinned host
+    memory) take the two-store path and equal the oracle's; the 8-byte aligned ones take one
+    8-byte store per peak."""
+    import torch
+    B = gpu
+    cap = 4096
+    acc = B.new_acc(CFG0)
+    for where in ("cuda", "pinned"):
+        if where == "cuda":
+            base = torch.zeros(2 * cap + 1, dtype=torch.int32, device="cuda")
+            nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+        else:
+            base = torch.zeros(2 * cap + 1, dtype=torch.int32, pin_memory=True)
+            nf = torch.zeros(1, dtype=torch.int64, pin_memory=True)
+        out = base[1:].view(cap, 2)
+        assert out.data_ptr() % 8 == 4
+        for e in range(4):
+            ev = synth.make_event(0, 720 + e)
+            say("4-byte aligned output,", where, "event", 720 + e)
+            xd, yd, zd = B.hits_to_device(ev.x, ev.y, ev.z)
+            B.ht_fill_peaks(CFG0, xd, yd, zd, acc, out, cap, nf)
+            torch.cuda.synchronize()
+            M, votes, oc, ov, on = oracle_run(CFG0, ev.x, ev.y, ev.z)
+            assert int(nf.cpu()[0]) == on
+            got = out.cpu().numpy().view(np.uint32)[:on]
+            assert np.array_equal(got[:, 0], oc) and np.array_equal(got[:, 1], ov)
+            assert int(base.cpu()[0]) == 0  # nothing written before the array
+
+
 def test_output_pointer_classification(gpu):
     """The host-side check that guards the peak outputs: device memory and mapped pinned host
     memory are accepted, unregistered host memory is refused. Only the classification is
