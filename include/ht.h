@@ -104,9 +104,10 @@ typedef struct ht_tuning {
                            counters fit in 56 KiB of LDS */
   int32_t group_tiles;  /* tiles per workgroup of the peak search: 16, 32 or 64 */
   int32_t cand_cap;     /* candidate-pool entries per tile, a power of two <= 4096: the cells
-                           at or above the threshold of all tiles share a pool of
-                           n_tiles * cand_cap entries; tiles that do not fit are searched
-                           densely (slower, same results) */
+                           at or above the threshold of all tiles share a pool of at least
+                           n_tiles * cand_cap entries (more for large events: a quarter of the
+                           bound 4 n_hits n_a / threshold, at most the cell count); tiles that
+                           do not fit are searched densely (slower, same results) */
   int32_t nt_store;     /* store kind of the fill's single write of the matrix: 0 ordinary
                            16-byte stores, 1 non-temporal 16-byte stores, 2 ordinary 4-byte
                            stores */

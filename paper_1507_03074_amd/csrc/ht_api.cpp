@@ -90,6 +90,7 @@ void host_tables(const ht_grid& g, std::vector<float>& a2, float& inv_db, std::v
 // ---------------------------------------------------------------------------------------------
 struct Tiling {
   int32_t rows, tiles_per_slab, n_tiles, cand_cap, lds_fill, group_tiles, nt_store, fill_tiles;
+  int32_t pool_bound;
 };
 
 static int env_int(const char* name, int def)
@@ -157,6 +158,8 @@ Tiling choose_tiling(const ht_grid& g)
   const int forced_ft = env_int("HT_FILL_TILES", 0);
   if (forced_ft > 0 && forced_ft <= 64 && (forced_ft & (forced_ft - 1)) == 0) ft = forced_ft;
   t.fill_tiles = ft;
+  // HT_POOL_BOUND=0: the pool holds n_tiles * cand_cap entries only (tests force overflow so)
+  t.pool_bound = env_int("HT_POOL_BOUND", 1) != 0 ? 1 : 0;
   ht_tuning tu;
   bool have = false;
   {
@@ -268,6 +271,7 @@ DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
   d.group_tiles = tl.group_tiles;
   d.nt_store = tl.nt_store;
   d.fill_tiles = tl.fill_tiles;
+  d.pool_bound = tl.pool_bound;
   d.phi_sectors = g.phi_sectors;
   // candidate test: enough workgroups to spread a few thousand candidates over the whole chip
   // in one pass (two candidates per wave), few enough that a near-empty event exits at once
@@ -288,6 +292,22 @@ bool direct_lists(const DevGrid& g, int64_t n)
   return g.lds_fill && (size_t)g.n_slabs * (size_t)std::max<int64_t>(n, 1) * 16 <= kDirectListMax;
 }
 
+// Candidate-pool entries for an event of up to n hits: cand_cap per tile, and at least a
+// quarter of the bound on the cells that can reach the threshold (a hit's records vote at most
+// once per A row, into at most four (theta, phi) cells, two with phi sectors: votes <= 4 n n_a,
+// candidates <= votes / T). Large events have far more candidates than cand_cap per tile (a
+// 40k-hit event on the paper grid about 2.6M, against 0.25 of its bound of 18M); a tile whose
+// candidates do not fit is searched densely, which is exact but slow.
+size_t pool_entries(const DevGrid& g, int64_t n)
+{
+  const size_t by_tiles = (size_t)g.n_tiles * (size_t)g.cand_cap;
+  const size_t cells = (size_t)g.n_theta * g.n_phi * g.n_a * g.n_b;
+  const size_t bound = g.pool_bound ? (size_t)std::max<int64_t>(n, 0) * (g.phi_sectors ? 2 : 4) *
+                                          (size_t)g.n_a / (size_t)g.threshold
+                                    : 0;
+  return std::min<size_t>(std::max(by_tiles, std::min(cells, bound / 4)), 0xfffffff0u);
+}
+
 size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct)
 {
   const size_t nn = (size_t)std::max<int64_t>(n, 0);
@@ -303,8 +323,8 @@ size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct)
   }
   b += al(4 * (size_t)g.n_tiles);             // tile_cnt
   b += al(4 * (size_t)g.n_tiles);             // tile_off
-  b += al(8 * (size_t)g.n_tiles * g.cand_cap);  // pool
-  b += al((size_t)g.n_tiles * g.cand_cap);      // pk_flag
+  b += al(8 * pool_entries(g, n));              // pool
+  b += al(pool_entries(g, n));                  // pk_flag
   b += al(4 * (size_t)g.n_tiles);               // ovf_list
   b += al(4 * (size_t)g.n_tiles);             // tile_pk
   b += al(4 * (size_t)n_groups(g));           // group_pk
@@ -335,7 +355,7 @@ void carve_event_scratch(const DevGrid& g, int64_t n, bool direct, char* p, EvDe
   }
   ev->tile_cnt = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->tile_off = (uint32_t*)take(4 * (size_t)g.n_tiles);
-  ev->pool_cap = (uint32_t)std::min<size_t>((size_t)g.n_tiles * g.cand_cap, 0xfffffff0u);
+  ev->pool_cap = (uint32_t)pool_entries(g, n);
   ev->pool = (uint2*)take(8 * (size_t)ev->pool_cap);
   ev->pk_flag = (uint8_t*)take((size_t)ev->pool_cap);
   ev->ovf_list = (uint32_t*)take(4 * (size_t)g.n_tiles);

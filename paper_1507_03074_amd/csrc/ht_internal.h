@@ -46,6 +46,7 @@ struct DevGrid {
   int32_t group_tiles;     // tiles per workgroup of the peak search (16, 32 or 64)
   int32_t nt_store;        // fill store kind: 0 16-byte, 1 non-temporal 16-byte, 2 4-byte
   int32_t fill_tiles;      // fill tiles per workgroup (filled in turn)
+  int32_t pool_bound;      // 1: large events get a candidate pool sized by their vote bound
   int32_t phi_sectors;     // 1: phi cells are independent sectors (no phi widening or neighbours)
   int32_t test_blocks;     // workgroups per event of the candidate test
   const float* a2;         // device [n_a]
@@ -75,7 +76,7 @@ struct EvDesc {
   uint32_t* tile_cnt;   // [n_tiles] candidates (cells >= threshold) per tile
   uint32_t* tile_off;   // [n_tiles] first pool entry of each tile's candidates, or kTileOverflow
   uint2* pool;          // [pool_cap] (cell, votes) of the candidates, ascending within a tile
-  uint32_t pool_cap;    // n_tiles * cand_cap
+  uint32_t pool_cap;    // entries: at least n_tiles * cand_cap, more for large events
   uint8_t* pk_flag;     // [pool_cap] 1 if the pool entry is a peak
   uint32_t* ovf_list;   // [n_tiles] tiles whose candidates did not fit the pool
   uint32_t* tile_pk;    // [n_tiles] peaks per tile

@@ -39,7 +39,7 @@ def gpu():
 
 @pytest.fixture()
 def env_tiling():
-    keys = ("HT_FILL_ROWS", "HT_CAND_CAP", "HT_FILL_LDS_BYTES", "HT_BATCH_GRAPH")
+    keys = ("HT_FILL_ROWS", "HT_CAND_CAP", "HT_FILL_LDS_BYTES", "HT_BATCH_GRAPH", "HT_POOL_BOUND")
     saved = {k: os.environ.get(k) for k in keys}
     yield
     for k, v in saved.items():
@@ -223,11 +223,12 @@ def test_paper_grid_tile_shapes_bit_exact(gpu):
             assert_same(CFG1, gM, gc, gv, gn, M, oc, ov, on, "rows %d store %d tpb %d" % (rows, nt, tpb))
 
 
-def test_candidate_overflow_uses_dense_path(gpu):
-    """With 2 candidate slots per tile, crowded tiles overflow and are searched densely; the
-    results must not change."""
+def test_candidate_overflow_uses_dense_path(gpu, env_tiling):
+    """With 2 candidate slots per tile (and the pool not sized by the event's vote bound),
+    crowded tiles overflow and are searched densely; the results must not change."""
     import torch
     B = gpu
+    os.environ["HT_POOL_BOUND"] = "0"
     B.ht_set_tuning(CFG0, cand_cap=2)
     try:
         for e in (0, 1, 2):
