@@ -429,6 +429,28 @@ def test_serve_paper_grid(gpu):
         assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
 
 
+def test_largest_served_event_bit_exact(gpu):
+    """The largest event of the served workload (40000 hits, about 2.6M cells at or above the
+    threshold on the paper grid): more candidates than cand_cap per tile of the default shape,
+    so its pool is sized by the vote bound. Plain call (default shape) and request loop against
+    the oracle."""
+    import torch
+    B = gpu
+    ev = max((synth.make_event(3, e) for e in range(40)), key=lambda e: e.n)
+    assert ev.n == 40000
+    say("largest served event: %d hits, plain path" % ev.n)
+    M, votes, oc, ov, on = oracle_run(CFG1, ev.x, ev.y, ev.z)
+    assert on > 1 << 15
+    gM, gc, gv, gn = gpu_fused(B, CFG1, ev.x, ev.y, ev.z, capacity=1 << 19)
+    assert_same(CFG1, gM, gc, gv, gn, M, oc, ov, on, "plain")
+    del gM
+    say("largest served event: request loop")
+    opts = B.ServeOpts(4 << 30, 1 << 19, 40000, 2, 2, 8, 0)
+    (c, v, n, tm), = serve_all(B, CFG1, [ev], opts)
+    assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov)
+    torch.cuda.empty_cache()
+
+
 def test_stress_event_full_size(gpu):
     """One 105600-hit event on the 8x32x2048x2048 grid (4 GiB of counts), bit-exact."""
     import torch
