@@ -881,14 +881,18 @@ __device__ __forceinline__ void count_peak(const DevGrid& g, const EvDesc& e, ui
 // from. Few candidates (at most two passes of the grid): half a wave (32 lanes) per candidate,
 // one lane per neighbour row, so a candidate costs one load per lane and a ballot, and the
 // whole test is about one memory round trip. Many candidates: one thread per candidate, its 27
-// row loads issued back to back. Each result goes to pk_flag; a peak adds one to its tile's and
-// its group's counts. Tiles whose candidates did not fit the pool are counted densely, one wave
-// per tile.
+// row loads issued back to back; each workgroup takes one contiguous run of the pool (whole
+// waves), so the waves of a CU test neighbouring cells and share their rows in the L1, and the
+// runs of one XCD are adjacent, so its L2 holds one region. Each result goes to pk_flag; a
+// peak adds one to its tile's and its group's counts. Tiles whose candidates did not fit the
+// pool are counted densely, one wave per tile.
 __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   EvDesc e = load_ev(ev0, evs);
   const int lane = threadIdx.x & 63, half = lane >> 5, k = lane & 31;
-  const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  // workgroups are dealt to the 8 XCDs in turn: give each XCD one contiguous run of blocks
+  const uint32_t blk = gridDim.x % 8u ? blockIdx.x : (blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
+  const uint32_t wave = blk * (kBlock / 64) + (threadIdx.x >> 6);
   const uint32_t n_waves = gridDim.x * (kBlock / 64);
   // this half-wave's first entry is loaded before the entry count is known (an index inside
   // the pool is always readable), so the count and the entry cost one round trip
@@ -920,8 +924,10 @@ __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, con
       }
     }
   } else {
-    const uint32_t n_threads = gridDim.x * kBlock;
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n_valid; i += n_threads) {
+    // the run length is a whole number of waves; the last runs may be short or empty
+    const uint32_t per = ((n_valid + gridDim.x - 1u) / gridDim.x + 63u) & ~63u;
+    const uint32_t i_end = min(n_valid, (blk + 1u) * per);
+    for (uint32_t i = blk * per + threadIdx.x; i < i_end; i += kBlock) {
       const uint2 cv = ld_cand(e.pool, i);
       const bool pk = is_peak(g, acc, cv.x, cv.y);
       gp(e.pk_flag)[i] = pk ? 1 : 0;
