@@ -189,6 +189,29 @@ def test_ragged_grids_bit_exact(gpu, spec):
         assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "seed %d" % seed)
 
 
+# The peak test gives each workgroup one contiguous run of the candidate pool once there are more
+# than four candidates per wave of its grid (max(16, min(1024, ceil(n_tiles / 16))) workgroups),
+# and numbers the runs per XCD when that grid is a multiple of 8. These grids have 495 tiles (31
+# workgroups: plain numbering), 384 (24: XCD numbering, not a power of two) and 192 (16), each with
+# thousands of candidates, so the runs end in ragged tails.
+MANY_CANDIDATES = [((5, 3, 257, 1000), 495), ((3, 4, 256, 1000), 384), ((4, 16, 130, 66), 192)]
+
+
+@pytest.mark.parametrize("shape,n_tiles", MANY_CANDIDATES, ids=lambda v: "x".join(map(str, v))
+                         if isinstance(v, tuple) else str(v))
+def test_many_candidates_every_run_layout_bit_exact(gpu, shape, n_tiles):
+    B = gpu
+    spec = synth.GridSpec(*shape, threshold=2)
+    assert B.ht_tiling(spec)["n_tiles"] == n_tiles
+    for seed in range(2):
+        say("many candidates", shape, "seed", seed)
+        x, y, z = random_hits(seed, 300)
+        gM, gc, gv, gn = gpu_fused(B, spec, x, y, z)
+        M, votes, oc, ov, on = oracle_run(spec, x, y, z)
+        assert int((M >= spec.threshold).sum()) > 16 * max(16, (n_tiles + 15) // 16)
+        assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "seed %d" % seed)
+
+
 @pytest.mark.parametrize("rows", [1, 2, 4, 8, 16, 32, 64])
 def test_every_tile_shape_bit_exact(gpu, rows):
     """Every launch shape the tuner can pick gives the same bits."""
