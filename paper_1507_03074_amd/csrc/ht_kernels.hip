@@ -37,6 +37,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBlock = 256;
 static_assert(kBlock == 256, "candidate emission splits a tile over four wave64s");
 constexpr int kGroupTiles = 64;  // largest group of tiles per peak workgroup (g.group_tiles)
+constexpr int kWalkChunks = 4;   // chunks of kBlock pool entries per round of the ordered peak walk
 
 // A launch's event descriptor: the kernel argument for one event, else evs[blockIdx.y]. The
 // descriptor array is read through the constant address space: both sources are then
@@ -814,15 +815,14 @@ __device__ __forceinline__ void tile_range(const DevGrid& g, int tile, uint32_t*
   *L = (uint32_t)rows * (uint32_t)g.n_b;
 }
 
-// Largest t with pre[t] <= f, given pre[0] <= f < pre[kGroupTiles].
+// Largest t with pre[t] <= f, given pre[0] <= f < pre[kGroupTiles] and pre non-decreasing: a
+// fixed number of halving steps, with no branch.
 __device__ __forceinline__ int group_tile_of(const uint32_t* pre, uint32_t f)
 {
-  int lo = 0, hi = kGroupTiles;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= f) lo = mid;
-    else hi = mid;
-  }
+  static_assert((kGroupTiles & (kGroupTiles - 1)) == 0, "halving search over a power of two");
+  int lo = 0;
+#pragma unroll
+  for (int step = kGroupTiles / 2; step > 0; step >>= 1) lo += pre[lo + step] <= f ? step : 0;
   return lo;
 }
 
@@ -954,7 +954,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, con
 
 // One workgroup per group of tiles: its output offset is the sum of the earlier groups' peak
 // counts; the group's pooled candidates are walked in order (tile by tile, each tile's chunk
-// ascending) and the flagged ones written out; tiles that did not fit the pool are re-scanned
+// ascending, kWalkChunks * kBlock of them per memory round trip) and the flagged ones written out; tiles that did not fit the pool are re-scanned
 // densely.
 __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
@@ -1014,28 +1014,40 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
   lds_barrier();
   const uint32_t total = s_pre[kGroupTiles];
   uint32_t run = 0;
-  for (uint32_t b0 = 0; b0 < total; b0 += kBlock) {
-    const uint32_t f = b0 + threadIdx.x;
-    bool pk = false;
-    int tl = 0;
-    uint2 cv = make_uint2(0u, 0u);
-    if (f < total) {
-      tl = group_tile_of(s_pre, f);
-      const size_t idx = (size_t)s_off[tl] + (f - s_pre[tl]);
-      // flag and entry in the same round trip
-      pk = gp(e.pk_flag)[idx] != 0;
-      cv = ld_cand(e.pool, idx);
+  // kWalkChunks chunks of kBlock candidates per round: the flags and entries of all of them are
+  // loaded, with no branch between the loads, before the first chunk is scanned, so a round
+  // costs one memory round trip. Positions past the group's total load its first candidate
+  // (always readable) and count as no peak.
+  for (uint32_t b0 = 0; b0 < total; b0 += kWalkChunks * kBlock) {  // uniform
+    uint32_t flag[kWalkChunks];
+    int tl[kWalkChunks];
+    uint2 cv[kWalkChunks];
+#pragma unroll
+    for (int k = 0; k < kWalkChunks; ++k) {
+      const uint32_t f = b0 + (uint32_t)k * kBlock + threadIdx.x;
+      const uint32_t fc = f < total ? f : 0u;
+      tl[k] = group_tile_of(s_pre, fc);
+      const size_t idx = (size_t)s_off[tl[k]] + (fc - s_pre[tl[k]]);
+      flag[k] = gp(e.pk_flag)[idx];
+      cv[k] = ld_cand(e.pool, idx);
     }
-    uint32_t tot;
-    const uint32_t pos = run + block_excl_scan(pk ? 1u : 0u, smem, &tot);
-    // the first candidate of a tile records how many of the group's pooled peaks precede it
-    if (f < total && f == s_pre[tl]) s_first[tl] = pos;
-    lds_barrier();
-    if (pk) {
-      const int64_t o = base + s_out[tl] + (pos - s_first[tl]);
-      if (o < e.cap) st_peak(e.out, o, cv.x, cv.y, a8);
+#pragma unroll
+    for (int k = 0; k < kWalkChunks; ++k) {
+      const uint32_t f0 = b0 + (uint32_t)k * kBlock;
+      if (f0 >= total) break;  // uniform
+      const uint32_t f = f0 + threadIdx.x;
+      const bool pk = f < total && flag[k] != 0u;
+      uint32_t tot;
+      const uint32_t pos = run + block_excl_scan(pk ? 1u : 0u, smem, &tot);
+      // the first candidate of a tile records how many of the group's pooled peaks precede it
+      if (f < total && f == s_pre[tl[k]]) s_first[tl[k]] = pos;
+      lds_barrier();
+      if (pk) {
+        const int64_t o = base + s_out[tl[k]] + (pos - s_first[tl[k]]);
+        if (o < e.cap) st_peak(e.out, o, cv[k].x, cv[k].y, a8);
+      }
+      run += tot;
     }
-    run += tot;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t* acc = e.acc;
