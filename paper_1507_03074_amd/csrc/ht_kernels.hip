@@ -891,7 +891,8 @@ __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, con
   EvDesc e = load_ev(ev0, evs);
   const int lane = threadIdx.x & 63, half = lane >> 5, k = lane & 31;
   // workgroups are dealt to the 8 XCDs in turn: give each XCD one contiguous run of blocks
-  const uint32_t blk = gridDim.x % 8u ? blockIdx.x : (blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
+  const uint32_t blk =
+      gridDim.x % 8u ? blockIdx.x : (blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
   const uint32_t wave = blk * (kBlock / 64) + (threadIdx.x >> 6);
   const uint32_t n_waves = gridDim.x * (kBlock / 64);
   // this half-wave's first entry is loaded before the entry count is known (an index inside
@@ -924,10 +925,11 @@ __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, con
       }
     }
   } else {
-    // the run length is a whole number of waves; the last runs may be short or empty
-    const uint32_t per = ((n_valid + gridDim.x - 1u) / gridDim.x + 63u) & ~63u;
-    const uint32_t i_end = min(n_valid, (blk + 1u) * per);
-    for (uint32_t i = blk * per + threadIdx.x; i < i_end; i += kBlock) {
+    // the run length is a whole number of waves; the last runs may be short or empty. Bounds
+    // and index are 64-bit: the pool may hold nearly 2^32 entries.
+    const uint64_t per = (((uint64_t)n_valid + gridDim.x - 1u) / gridDim.x + 63u) & ~(uint64_t)63u;
+    const uint64_t i_end = min((uint64_t)n_valid, (uint64_t)(blk + 1u) * per);
+    for (uint64_t i = (uint64_t)blk * per + threadIdx.x; i < i_end; i += kBlock) {
       const uint2 cv = ld_cand(e.pool, i);
       const bool pk = is_peak(g, acc, cv.x, cv.y);
       gp(e.pk_flag)[i] = pk ? 1 : 0;
@@ -954,8 +956,8 @@ __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, con
 
 // One workgroup per group of tiles: its output offset is the sum of the earlier groups' peak
 // counts; the group's pooled candidates are walked in order (tile by tile, each tile's chunk
-// ascending, kWalkChunks * kBlock of them per memory round trip) and the flagged ones written out; tiles that did not fit the pool are re-scanned
-// densely.
+// ascending, kWalkChunks * kBlock of them per memory round trip) and the flagged ones written
+// out; tiles that did not fit the pool are re-scanned densely.
 __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   __shared__ uint32_t s_pre[kGroupTiles + 1];
