@@ -495,6 +495,37 @@ def ctypes_stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def bench_crowded(B, torch, synth, steps, tuning=None):
+    """Stage times on the smallest, median and largest of 40 events of workload 3 (lognormal
+    5k-40k hits on the paper grid), at the given launch shape or the library's default. The
+    largest event pools 2.6M candidates, so its peak stage runs the many-candidate test."""
+    spec = synth.WORKLOADS[3].grid
+    if tuning:
+        B.ht_set_tuning(spec, B.Tuning(*[int(v) for v in tuning.split(",")]))
+    evs = sorted((synth.make_event(3, e) for e in range(40)), key=lambda e: e.n)
+    cap = 1 << 19
+    acc = B.new_acc(spec)
+    out, nf = B.new_peaks(cap)
+    res = {"workload": synth.WORKLOADS[3].name, "tuning": B.ht_get_tuning(spec).as_dict(), "events": []}
+    for ev in (evs[0], evs[len(evs) // 2], evs[-1]):
+        x, y, z = B.hits_to_device(ev.x, ev.y, ev.z)
+        for _ in range(5):
+            B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+        torch.cuda.synchronize()
+        B.ht_profile_read("fill", reset=True)
+        B.ht_profile_enable(1)
+        for _ in range(steps):
+            B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+        torch.cuda.synchronize()
+        B.ht_profile_enable(0)
+        us = {st: round(B.ht_profile_read(st)[0] / steps * 1e3, 1) for st in ("prep", "fill", "peaks")}
+        B.ht_profile_read("fill", reset=True)
+        res["events"].append({"hits": ev.n, "peaks": int(nf.item()), "stage_us": us})
+    if tuning:
+        B.ht_set_tuning(spec)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -512,6 +543,9 @@ def main():
                     help="for hardware-counter runs: a 256 MiB copy (the byte-counter reference) "
                          "three times, then --steps steps untimed, then three plain atomic fills; "
                          "prints one line")
+    ap.add_argument("--crowded", action="store_true",
+                    help="stage times on small, median and crowded events of the served stream "
+                         "(workload 3) at the --tuning shape or the default; prints one line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path. Events are "
@@ -527,6 +561,10 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     torch.cuda.set_device(0)
+    if args.crowded:
+        print(json.dumps({"crowded": bench_crowded(B, torch, synth, min(args.steps, 50), args.tuning)}),
+              flush=True)
+        return
     workload = 1
     spec = synth.WORKLOADS[workload].grid
     cap = 4096
