@@ -24,6 +24,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "events/s + Gvotes/s on 1 MI355X; p50/p99 event latency, served vs plain"
 HBM_PEAK_GBS = 8000.0
+# Launch shape of the timed loop (rows, group_tiles, cand_cap, nt_store, tiles_per_block; 0 or -1
+# for the library's default of a field), measured fastest on MI355X with the matrices cycled;
+# the committed profiles are taken at it.
+PINNED_TUNING = "4,16,0,1,1"
 
 
 def log(*a):
@@ -149,17 +153,21 @@ def measure_peaks(B, torch, acc_bytes, big_bytes=2 << 30):
 
 def bench_batched(B, torch, synth, workload, n_events, reps, capacity, tune_batch=False):
     """One ht_fill_peaks_batch call (a captured graph) over n_events events of the workload;
-    with tune_batch, the launch shape comes from the autotuner run on this batch (and the grid's
-    previous shape is restored afterwards)."""
+    with tune_batch, the launch shape comes from the autotuner run on another batch of the same
+    workload (events n_events .. 2 n_events - 1, kept apart from the timed ones), and the grid's
+    previous shape is restored afterwards."""
     spec = synth.WORKLOADS[workload].grid
     evs = [synth.make_event(workload, e) for e in range(n_events)]
     tuned = None
     if tune_batch:
         from paper_1507_03074_amd import tune
         before = B.ht_get_tuning(spec)
-        rep = tune.autotune_batch(spec, [(e.x, e.y, e.z) for e in evs], capacity=capacity)
+        tevs = [synth.make_event(workload, n_events + e) for e in range(n_events)]
+        rep = tune.autotune_batch(spec, [(e.x, e.y, e.z) for e in tevs], capacity=capacity)
+        del tevs
         tuned = {"best": rep["best"], "default_ms_per_batch": round(rep["default_ms_per_batch"], 3),
-                 "candidates": len(rep["candidates"])}
+                 "candidates": len(rep["candidates"]),
+                 "events": "workload %d, seeds %d-%d" % (workload, n_events, 2 * n_events - 1)}
     xs = np.concatenate([e.x for e in evs])
     ys = np.concatenate([e.y for e in evs])
     zs = np.concatenate([e.z for e in evs])
@@ -371,19 +379,30 @@ def bench_transfers(B, torch, synth, spec, sizes=(500, 1000, 2000, 4000, 8000), 
     return res
 
 
+KERNEL_SOURCES = ("ht_device.h", "ht_kernels.hip", "ht_fill_rows.hip")
+
+
+def kernel_sources_sha256():
+    """SHA-256 over the kernel sources, in a fixed order: counters taken on other sources no
+    longer describe the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1507_03074_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def counter_traffic(tuning: dict):
     """HBM bytes per fill launch from the committed FETCH_SIZE / WRITE_SIZE counter summary
     (each counter scaled by what it reads for a copy of known size), or None when the summary
     was taken on other kernel sources or with another fill shape (A rows per tile, store kind,
     tiles per workgroup)."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "k_fill_paper-event_counters.md")
-    src = os.path.join(ROOT, "paper_1507_03074_amd", "csrc", "ht_kernels.hip")
     try:
         text = open(path).read()
         recs = [json.loads(m) for m in re.findall(r"```json\n(.*?)\n```", text, re.S)]
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_sources_sha256()
     except (OSError, ValueError):
         return None
     shape = [tuning[f] for f in ("rows", "nt_store", "tiles_per_block")]
@@ -526,23 +545,32 @@ def bench_crowded(B, torch, synth, steps, tuning=None):
     return res
 
 
+def pinned_tuning(text):
+    return [int(v) for v in text.split(",")]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--events", type=int, default=16, help="distinct resident events cycled")
+    ap.add_argument("--matrices", type=int, default=16,
+                    help="vote matrices cycled by the timed loop (16 x 256 MiB = 4 GiB, far past "
+                         "the 256 MB last-level cache, so every matrix write reaches HBM)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="main line only (no extra workloads)")
-    ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
-    ap.add_argument("--tuning", default=None,
-                    help="rows,group_tiles,cand_cap,nt_store,tiles_per_block: this launch shape "
-                         "instead of autotuning")
+    ap.add_argument("--tuning", default=PINNED_TUNING,
+                    help="rows,group_tiles,cand_cap,nt_store,tiles_per_block of the timed loop "
+                         "(default: the shape pinned here, which the committed profiles use)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="search the launch shape on four separate events (cycling --matrices "
+                         "matrices) instead of using --tuning")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: a 256 MiB copy (the byte-counter reference) "
-                         "three times, then --steps steps untimed, then three plain atomic fills; "
-                         "prints one line")
+                         "three times, then --steps steps of the timed loop untimed, then three "
+                         "plain atomic fills; prints one line")
     ap.add_argument("--crowded", action="store_true",
                     help="stage times on small, median and crowded events of the served stream "
                          "(workload 3) at the --tuning shape or the default; prints one line")
@@ -557,12 +585,12 @@ def main():
     from paper_1507_03074_amd import binding as B
     from paper_1507_03074_amd import synth
 
-    if not os.path.exists(B.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
+    from paper_1507_03074_amd import build as hbuild
+    hbuild.ensure_built()  # a missing or stale library is rebuilt, never measured
     torch.cuda.set_device(0)
     if args.crowded:
-        print(json.dumps({"crowded": bench_crowded(B, torch, synth, min(args.steps, 50), args.tuning)}),
+        tuning = None if args.tuning == PINNED_TUNING else args.tuning
+        print(json.dumps({"crowded": bench_crowded(B, torch, synth, min(args.steps, 50), tuning)}),
               flush=True)
         return
     workload = 1
@@ -571,22 +599,23 @@ def main():
     log("generating %d events of workload %d" % (args.events, workload))
     evs = [synth.make_event(workload, e) for e in range(args.events)]
     dev_hits = [B.hits_to_device(e.x, e.y, e.z) for e in evs]
-    acc = B.new_acc(spec)
+    mats = [B.new_acc(spec) for _ in range(max(1, args.matrices))]
+    acc = mats[0]
     out = torch.empty((args.events, cap, 2), dtype=torch.int32, device="cuda")
     nf = torch.zeros(args.events, dtype=torch.int64, device="cuda")
     h_out = torch.empty((args.events, cap, 2), dtype=torch.int32, pin_memory=True)
     h_nf = torch.zeros(args.events, dtype=torch.int64, pin_memory=True)
     stream = torch.cuda.current_stream()
 
-    def step(k):
-        # the peak kernel writes the peak list and its count straight into pinned host memory
+    def step(k, ms=mats):
+        # event k % E into matrix k % M; the peak kernel writes the peak list and its count
+        # straight into pinned host memory
         i = k % args.events
         x, y, z = dev_hits[i]
-        B.ht_fill_peaks(spec, x, y, z, acc, h_out[i], cap, h_nf[i:i + 1], stream)
+        B.ht_fill_peaks(spec, x, y, z, ms[k % len(ms)], h_out[i], cap, h_nf[i:i + 1], stream)
 
     if args.counters:
-        if args.tuning:
-            B.ht_set_tuning(spec, B.Tuning(*[int(v) for v in args.tuning.split(",")]))
+        B.ht_set_tuning(spec, B.Tuning(*pinned_tuning(args.tuning)))
         copy_bytes = 256 << 20
         src = torch.zeros(copy_bytes // 4, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
@@ -602,21 +631,22 @@ def main():
             B.ht_fill(spec, x, y, z, acc, stream, atomic=True)
         torch.cuda.synchronize()
         print(json.dumps({"counters_run": True, "copy_bytes": copy_bytes, "copies": 3,
-                          "steps": args.steps, "atomic_fills": 3,
+                          "steps": args.steps, "matrices": len(mats), "atomic_fills": 3,
                           "tuning": B.ht_get_tuning(spec).as_dict()}), flush=True)
         return
 
-    # launch shape from the autotuner (every candidate is gated on bit-exact results)
-    tuned = None
-    if args.tuning:
-        B.ht_set_tuning(spec, B.Tuning(*[int(v) for v in args.tuning.split(",")]))
-        tuned = {"given": args.tuning}
-    elif not args.no_tune:
+    # launch shape: the pinned one (the committed profiles are taken at it), or a search on
+    # events kept apart from the timed set (every candidate gated on bit-exact results)
+    if args.autotune:
         from paper_1507_03074_amd import tune
         log("autotuning the launch shape")
-        rep = tune.autotune(spec, [(e.x, e.y, e.z) for e in evs[:4]], reps=30)
+        tevs = [synth.make_event(workload, 100 + e) for e in range(4)]
+        rep = tune.autotune(spec, [(e.x, e.y, e.z) for e in tevs], reps=30, n_acc=min(len(mats), 8))
         tuned = {"best": rep["best"], "default_us_per_event": round(rep["default_us_per_event"], 2),
-                 "candidates": len(rep["candidates"])}
+                 "candidates": len(rep["candidates"]), "events": "workload 1, seeds 100-103"}
+    else:
+        B.ht_set_tuning(spec, B.Tuning(*pinned_tuning(args.tuning)))
+        tuned = {"pinned": args.tuning}
 
     # votes per event (the matrix sum; equal to the oracle's count by the parity tests)
     votes = []
@@ -625,27 +655,33 @@ def main():
         B.ht_fill(spec, x, y, z, acc)
         votes.append(int(acc.sum(dtype=torch.int64).item()))
 
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
+    def timed_loop(ms, steps):
+        """K steps between two device synchronisations; the library records a HIP event pair
+        around each fill launch on `stream` (the fill kernel's own duration, for the roofline);
+        nothing else is timed inside it."""
+        for k in range(args.warmup):
+            step(k, ms)
+        torch.cuda.synchronize()
+        B.ht_profile_read("fill", reset=True)
+        B.ht_profile_enable(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(k, ms)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        B.ht_profile_enable(0)
+        f_ms, f_n = B.ht_profile_read("fill", reset=True)
+        return t1 - t0, f_ms / 1000.0 / max(f_n, 1)
 
-    # timed region: the library records a HIP event pair around each fill launch on `stream`
-    # (the fill kernel's own duration, for the roofline); nothing else is timed inside it
-    B.ht_profile_read("fill", reset=True)
-    B.ht_profile_enable(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(k)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    B.ht_profile_enable(0)
-    fill_ms, fill_n = B.ht_profile_read("fill", reset=True)
-    elapsed = t1 - t0
+    # the headline: every event's matrix its own (4 GiB in all), so the writes reach HBM
+    elapsed, fill_avg_s = timed_loop(mats, args.steps)
     ms_per_step = 1000.0 * elapsed / args.steps
     ev_per_s = args.steps / elapsed
     total_votes = sum(votes[k % args.events] for k in range(args.steps))
     nfound = h_nf.numpy().copy()
+    # beside it: one matrix rewritten every step, which stays in the 256 MB last-level cache
+    elapsed1, fill_avg1_s = timed_loop([acc], args.steps)
 
     # outside the timed region: the same loop with events around every stage (breakdown), and
     # with no events at all (the cost of the timing events themselves)
@@ -674,12 +710,13 @@ def main():
     for x, y, z in dev_hits:
         info, _, _ = B.ht_debug_hit_values(spec, x, y, z)
         entries.append(int(info[:, 3].sum().item()))
-    fill_avg_s = fill_ms / 1000.0 / max(fill_n, 1)
     # algorithmic bytes of one fill launch: the matrix written once (4 B per cell) plus each
     # bucketed (hit, cell) record read once (16 B)
     hit_entries = float(np.mean(entries))
     alg_bytes = 4.0 * cells + 16.0 * hit_entries
     achieved = alg_bytes / fill_avg_s / 1e9
+    achieved1 = alg_bytes / fill_avg1_s / 1e9
+    tuning_now = B.ht_get_tuning(spec).as_dict()
     line = {
         "metric": METRIC,
         "value": round(ev_per_s, 2),
@@ -695,8 +732,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": synth.WORKLOADS[workload].name, "hits_per_event": 5000,
                    "grid": list(spec.shape), "threshold": spec.threshold,
-                   "path": "ht_fill_peaks (fused), peak list written to pinned host memory", "tile_rows": t["rows"],
-                   "resident_events": args.events},
+                   "path": "ht_fill_peaks (fused), peak list written to pinned host memory",
+                   "tile_rows": t["rows"], "resident_events": args.events,
+                   "matrices_cycled": len(mats), "matrix_bytes_cycled": 4 * cells * len(mats)},
         "gvotes_per_s": round(total_votes / elapsed / 1e9, 3),
         "votes_per_event": round(float(np.mean(votes)), 1),
         "fill_gvotes_per_s": round(np.mean(votes) / fill_avg_s / 1e9, 3),
@@ -705,11 +743,20 @@ def main():
         "ms_per_step_without_events": round(1000.0 * (t3 - t2) / n_extra, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(B.ht_get_tuning(spec).as_dict()),
+                     "traffic": counter_traffic(tuning_now),
                      "kernel": "k_fill", "alg_bytes_per_launch": alg_bytes,
-                     "fill_kernel_us": round(fill_avg_s * 1e6, 2)},
+                     "fill_kernel_us": round(fill_avg_s * 1e6, 2),
+                     "matrices_cycled": len(mats)},
+        "single_matrix_loop": {
+            "note": "one 256 MiB matrix rewritten every step: it stays in the 256 MB last-level "
+                    "cache, so this is not an HBM figure",
+            "events_per_s": round(args.steps / elapsed1, 2),
+            "ms_per_step": round(1000.0 * elapsed1 / args.steps, 4),
+            "fill_kernel_us": round(fill_avg1_s * 1e6, 2),
+            "fill_alg_GBs": round(achieved1, 1),
+            "frac_of_8TBs": round(achieved1 / HBM_PEAK_GBS, 4)},
         "peaks_per_event": round(float(np.mean(nfound)), 1),
-        "tuning": B.ht_get_tuning(spec).as_dict(),
+        "tuning": tuning_now,
         "autotune": tuned,
     }
     # the plain baseline: zero the matrix, one global atomicAdd per vote (paper-style kernel)
@@ -718,17 +765,48 @@ def main():
     B.ht_profile_enable(True)
     for k in range(min(args.steps, 50)):
         x, y, z = dev_hits[k % args.events]
-        B.ht_fill(spec, x, y, z, acc, stream, atomic=True)
+        B.ht_fill(spec, x, y, z, mats[k % len(mats)], stream, atomic=True)
     torch.cuda.synchronize()
     B.ht_profile_enable(False)
     fa_ms, fa_n = B.ht_profile_read("fill_atomic", reset=True)
     fa_s = fa_ms / 1e3 / max(fa_n, 1)
     line["plain_atomic_fill"] = {"ms": round(fa_s * 1e3, 4),
                                  "gvotes_per_s": round(np.mean(votes) / fa_s / 1e9, 3)}
+    # plain per-event latency (launch to result on the host), one event at a time, hits resident
+    lat = []
+    for k in range(100):
+        i = k % args.events
+        x, y, z = dev_hits[i]
+        ts = time.perf_counter()
+        B.ht_fill_peaks(spec, x, y, z, mats[k % len(mats)], h_out[i], cap, h_nf[i:i + 1], stream)
+        stream.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+    line["plain_latency_ms"] = {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)}
+    # plain per-event path with the hit upload: hits in pinned host memory, copied to the device
+    # (three arrays), fill and peaks, the peak list written to pinned host memory, synchronised;
+    # one event at a time (the PCIe-inclusive rate)
+    h_hits = [tuple(torch.from_numpy(np.ascontiguousarray(a)).pin_memory() for a in (e.x, e.y, e.z))
+              for e in evs]
+    lat = []
+    t0 = time.perf_counter()
+    for k in range(200):
+        i = k % args.events
+        x, y, z = dev_hits[i]
+        ts = time.perf_counter()
+        for d, h in zip((x, y, z), h_hits[i]):
+            d.copy_(h, non_blocking=True)
+        B.ht_fill_peaks(spec, x, y, z, mats[k % len(mats)], h_out[i], cap, h_nf[i:i + 1], stream)
+        stream.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+    dt = time.perf_counter() - t0
+    line["plain_with_upload"] = {"events_per_s": round(200 / dt, 1),
+                                 "p50_ms": round(percentile(lat, 50), 4),
+                                 "p99_ms": round(percentile(lat, 99), 4)}
     pk = measure_peaks(B, torch, 4 * cells)
     line["measured_peaks"] = pk
     line["fill_frac_of_measured_write"] = round(achieved / pk["hbm_write_GBs"], 4)
-    line["fill_frac_of_matrix_sized_write"] = round(achieved / pk["matrix_sized_buffer"]["write_GBs"], 4)
+    line["single_matrix_loop"]["fill_frac_of_matrix_sized_write"] = round(
+        achieved1 / pk["matrix_sized_buffer"]["write_GBs"], 4)
     line["fill_votes_vs_atomic_roofline"] = round(
         line["fill_gvotes_per_s"] / pk["atomic_rand_Gops"], 3)
     # physics check of the peak lists against the generator's truth (Fig. 1 analogue)
@@ -748,22 +826,11 @@ def main():
         "rho_resolution_lsq_fit": round(float(np.mean([p["rho_resolution_fit"] for p in phys])), 6),
         "phi_resolution_lsq_fit_mrad": round(1e3 * float(np.mean([p["phi_resolution_fit"] for p in phys])), 4),
         "tracks_in_acceptance_per_event": round(float(np.mean([p["in_acceptance"] for p in phys])), 1)}
-
-    # plain per-event latency (launch to result on the host), one event at a time
-    lat = []
-    for k in range(100):
-        i = k % args.events
-        x, y, z = dev_hits[i]
-        ts = time.perf_counter()
-        B.ht_fill_peaks(spec, x, y, z, acc, h_out[i], cap, h_nf[i:i + 1], stream)
-        stream.synchronize()
-        lat.append((time.perf_counter() - ts) * 1e3)
-    line["plain_latency_ms"] = {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)}
     log("sector variant")
     line["sectors"] = bench_sectors(B, torch, synth, evs, dev_hits, min(args.steps, 300))
     if not args.quick:
         line["two_streams"] = bench_two_streams(B, torch, spec, dev_hits, h_out, h_nf, cap, args.steps)
-        del acc, out
+        del acc, out, mats
         torch.cuda.empty_cache()
         log("batched workload 2")
         line["batched"] = bench_batched(B, torch, synth, 2, 100, 5, 1 << 13, tune_batch=True)

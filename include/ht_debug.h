@@ -49,6 +49,15 @@ int ht_fill_atomic(const ht_grid* grid, const float* x, const float* y, const fl
 int ht_tiling(const ht_grid* grid, int32_t* rows, int32_t* n_tiles, int32_t* cand_cap,
               int32_t* lds_fill);
 
+/* ht_debug_batch_plan: the slab-list layout ht_fill_peaks_batch picks for these events on this
+ * grid at the current launch shape, computed on the host with the same code (no device work):
+ * *direct = 1 for direct per-slab lists, 0 for the counting sort into packed lists (used when
+ * an event's direct lists would pass 512 MiB or all events' scratch would pass 8 GiB);
+ * *scratch_bytes = the device scratch the batch needs. events: host ht_event[n_events].
+ * Errors: HT_EINVAL (grid, events, n_events outside [1, 65535], NULL outputs). */
+int ht_debug_batch_plan(const ht_grid* grid, const ht_event* events, int32_t n_events,
+                        int32_t* direct, int64_t* scratch_bytes);
+
 /* ht_profile_enable: per-stage timing of later calls. mode 1: a HIP event (created without the
  * system-scope fence) is recorded on the call's stream before and after each stage ("prep",
  * "fill", "fill_atomic", "candidates", "peaks"); mode 2: around the fill stages only ("fill",

@@ -90,7 +90,7 @@ EXPORTS = ["ht_set_tuning", "ht_get_tuning", "ht_tables", "ht_fill", "ht_peaks",
            "ht_last_error", "ht_debug_hit_values", "ht_debug_unary", "ht_fill_atomic", "ht_tiling",
            "ht_profile_enable", "ht_profile_read", "ht_bench_hbm_write", "ht_bench_hbm_read",
            "ht_bench_copy", "ht_bench_atomic_rand", "ht_bench_lds_atomic", "ht_readout",
-           "ht_debug_pointer_kind"]
+           "ht_debug_pointer_kind", "ht_debug_batch_plan"]
 
 _lib = None
 
@@ -123,6 +123,8 @@ def lib():
         "ht_debug_unary": ([vp, vp, vp, i64, vp], ctypes.c_int),
         "ht_readout": ([gp, vp, vp, i64, vp, vp], ctypes.c_int),
         "ht_debug_pointer_kind": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "ht_debug_batch_plan": ([gp, ctypes.POINTER(Event), i32, ctypes.POINTER(i32),
+                                 ctypes.POINTER(i64)], ctypes.c_int),
         "ht_serve_create": ([gp, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)], ctypes.c_int),
         "ht_serve_submit": ([vp, f32p, f32p, f32p, i64, ctypes.POINTER(ctypes.c_uint64)],
                             ctypes.c_int),
@@ -301,6 +303,18 @@ def ht_debug_pointer_kind(ptr: int) -> int:
     return k.value
 
 
+def ht_debug_batch_plan(spec, n_hits):
+    """(direct, scratch_bytes) that ht_fill_peaks_batch would use for events of these sizes at
+    the grid's current launch shape (host only)."""
+    g = make_grid(spec)
+    arr = (Event * len(n_hits))(*[Event(0, int(n), 0, 0) for n in n_hits])
+    d = ctypes.c_int32()
+    b = ctypes.c_int64()
+    check(lib().ht_debug_batch_plan(ctypes.byref(g), arr, len(n_hits), ctypes.byref(d),
+                                    ctypes.byref(b)))
+    return bool(d.value), b.value
+
+
 def ht_debug_hit_values(spec, x, y, z, stream=None):
     import torch
     g = make_grid(spec)
@@ -362,8 +376,13 @@ def hits_to_device(x, y, z, device="cuda"):
     return tuple(torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(device) for a in (x, y, z))
 
 
-def peaks_to_host(out, n_found, capacity):
+def peaks_to_host(out, n_found, capacity, allow_truncation=False):
+    """(cells, votes, n_found) of a peak list on the device. The count is the total found; when
+    it exceeds the capacity the list holds only the first `capacity` peaks, and this raises
+    HTError(HT_EOVERFLOW) unless allow_truncation is set."""
     n = int(n_found.item())
+    if n > capacity and not allow_truncation:
+        raise HTError(HT_EOVERFLOW, "%d peaks found, the output holds %d" % (n, capacity))
     k = min(n, capacity)
     arr = as_u32(out[:k]) if k else np.zeros((0, 2), np.uint32)
     return arr[:, 0].copy(), arr[:, 1].copy(), n
@@ -376,18 +395,18 @@ def fill(spec, x, y, z, acc=None, stream=None, atomic=False):
     return acc
 
 
-def peaks(spec, acc, capacity=1 << 20, stream=None):
+def peaks(spec, acc, capacity=1 << 20, stream=None, allow_truncation=False):
     out, nf = new_peaks(capacity, acc.device)
     ht_peaks(spec, acc, out, capacity, nf, stream)
-    return peaks_to_host(out, nf, capacity)
+    return peaks_to_host(out, nf, capacity, allow_truncation)
 
 
-def fill_peaks(spec, x, y, z, capacity=1 << 20, acc=None, stream=None):
+def fill_peaks(spec, x, y, z, capacity=1 << 20, acc=None, stream=None, allow_truncation=False):
     if acc is None:
         acc = new_acc(spec, device=x.device)
     out, nf = new_peaks(capacity, x.device)
     ht_fill_peaks(spec, x, y, z, acc, out, capacity, nf, stream)
-    cells, votes, n = peaks_to_host(out, nf, capacity)
+    cells, votes, n = peaks_to_host(out, nf, capacity, allow_truncation)
     return acc, cells, votes, n
 
 
@@ -397,8 +416,11 @@ class BatchResult:
     peaks: list       # per event (cells, votes, n_found)
 
 
-def fill_peaks_batch(spec, hits, capacity=1 << 16, acc=None, stream=None, device="cuda"):
-    """hits: list of (x, y, z) host arrays. Returns per-event peak lists and the accumulators."""
+def fill_peaks_batch(spec, hits, capacity=1 << 16, acc=None, stream=None, device="cuda",
+                     allow_truncation=False):
+    """hits: list of (x, y, z) host arrays. Returns per-event peak lists and the accumulators.
+    Raises HTError(HT_EOVERFLOW) when an event has more peaks than `capacity`, unless
+    allow_truncation is set (its list then holds the first `capacity` peaks)."""
     import torch
     xs = np.concatenate([np.asarray(h[0], np.float32) for h in hits]) if hits else np.zeros(0, np.float32)
     ys = np.concatenate([np.asarray(h[1], np.float32) for h in hits]) if hits else np.zeros(0, np.float32)
@@ -419,6 +441,9 @@ def fill_peaks_batch(spec, hits, capacity=1 << 16, acc=None, stream=None, device
     nfh = nf.cpu().numpy()
     outh = as_u32(out)
     for i in range(len(hits)):
+        if int(nfh[i]) > capacity and not allow_truncation:
+            raise HTError(HT_EOVERFLOW, "event %d: %d peaks found, the output holds %d"
+                          % (i, int(nfh[i]), capacity))
         k = min(int(nfh[i]), capacity)
         seg = outh[i * capacity: i * capacity + k]
         res.append((seg[:, 0].copy(), seg[:, 1].copy(), int(nfh[i])))

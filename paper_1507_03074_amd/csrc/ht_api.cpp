@@ -91,6 +91,7 @@ void host_tables(const ht_grid& g, std::vector<float>& a2, float& inv_db, std::v
 struct Tiling {
   int32_t rows, tiles_per_slab, n_tiles, cand_cap, lds_fill, group_tiles, nt_store, fill_tiles;
   int32_t pool_bound;
+  int32_t packed_lists;
 };
 
 static int env_int(const char* name, int def)
@@ -160,6 +161,9 @@ Tiling choose_tiling(const ht_grid& g)
   t.fill_tiles = ft;
   // HT_POOL_BOUND=0: the pool holds n_tiles * cand_cap entries only (tests force overflow so)
   t.pool_bound = env_int("HT_POOL_BOUND", 1) != 0 ? 1 : 0;
+  // HT_PACKED_LISTS=1: every event takes the counting sort into packed slab lists, the layout
+  // that large batches and very large events use, so that tests reach it on small grids
+  t.packed_lists = env_int("HT_PACKED_LISTS", 0) != 0 ? 1 : 0;
   ht_tuning tu;
   bool have = false;
   {
@@ -273,6 +277,7 @@ DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
   d.fill_tiles = tl.fill_tiles;
   d.pool_bound = tl.pool_bound;
   d.phi_sectors = g.phi_sectors;
+  d.packed_lists = tl.packed_lists;
   // candidate test: enough workgroups to spread a few thousand candidates over the whole chip
   // in one pass (two candidates per wave), few enough that a near-empty event exits at once
   d.test_blocks = std::max(16, std::min(1024, (tl.n_tiles + 15) / 16));
@@ -289,7 +294,8 @@ static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 
 bool direct_lists(const DevGrid& g, int64_t n)
 {
-  return g.lds_fill && (size_t)g.n_slabs * (size_t)std::max<int64_t>(n, 1) * 16 <= kDirectListMax;
+  return g.lds_fill && !g.packed_lists &&
+         (size_t)g.n_slabs * (size_t)std::max<int64_t>(n, 1) * 16 <= kDirectListMax;
 }
 
 // Candidate-pool entries for an event of up to n hits: cand_cap per tile, and at least a
@@ -603,6 +609,31 @@ int check_accessible(const void* ptr, const char* what)
   return HT_OK;
 }
 
+// Scratch layout of a batch: direct slab lists for every event when each event allows them and
+// their scratch totals at most 8 GiB, else the counting sort for all (the 16-event batch of
+// 105600-hit events on the 8x32x2048x2048 grid takes the counting sort). Returns whether the
+// lists are direct; offs[i] is event i's scratch offset, *total the bytes of all of them.
+bool plan_batch(const DevGrid& g, const ht_event* events, int n_events, std::vector<size_t>* offs,
+                size_t* total, int64_t* max_hits)
+{
+  bool direct = g.lds_fill != 0;
+  size_t direct_bytes = 0;
+  for (int i = 0; i < n_events; ++i) {
+    direct = direct && direct_lists(g, events[i].n_hits);
+    direct_bytes += event_scratch_bytes(g, events[i].n_hits, true);
+  }
+  if (direct_bytes > kBatchDirectMax) direct = false;
+  offs->assign((size_t)n_events, 0);
+  *total = 0;
+  *max_hits = 0;
+  for (int i = 0; i < n_events; ++i) {
+    *max_hits = std::max(*max_hits, events[i].n_hits);
+    (*offs)[i] = *total;
+    *total += event_scratch_bytes(g, events[i].n_hits, direct);
+  }
+  return direct;
+}
+
 int run_event(const ht_grid* grid, const float* x, const float* y, const float* z, int64_t n,
               uint32_t* acc, ht_peak* out, int64_t cap, int64_t* n_found, void* stream,
               bool do_fill, bool do_peaks, bool force_atomic)
@@ -731,7 +762,7 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
   if (n_events < 0 || n_events > 65535) return fail(HT_EINVAL, "n_events must be in [0, 65535]");
   if (n_events == 0) return HT_OK;
   if (!events || !acc || !n_found) return fail(HT_EINVAL, "NULL batch argument");
-  int64_t max_hits = 0, total_scratch = 0;
+  int64_t max_hits = 0;
   int rc = validate_grid(grid);
   if (rc) return rc;
   for (int32_t i = 0; i < n_events; ++i) {
@@ -745,21 +776,11 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
   Prepared p;
   if ((rc = prepare(grid, stream, &p))) return rc;
   if ((rc = check_accessible(out, "out")) || (rc = check_accessible(n_found, "n_found"))) return rc;
-  std::vector<size_t> offs(n_events);
-  bool direct = p.g.lds_fill != 0;
-  size_t direct_bytes = 0;
-  for (int32_t i = 0; i < n_events; ++i) {
-    direct = direct && direct_lists(p.g, events[i].n_hits);
-    direct_bytes += event_scratch_bytes(p.g, events[i].n_hits, true);
-  }
-  if (direct_bytes > ((size_t)8 << 30)) direct = false;
-  for (int32_t i = 0; i < n_events; ++i) {
-    max_hits = std::max(max_hits, events[i].n_hits);
-    offs[i] = (size_t)total_scratch;
-    total_scratch += (int64_t)event_scratch_bytes(p.g, events[i].n_hits, direct);
-  }
+  std::vector<size_t> offs;
+  size_t total_scratch = 0;
+  const bool direct = plan_batch(p.g, events, n_events, &offs, &total_scratch, &max_hits);
   Workspace* w;
-  if ((rc = get_workspace(p.dev, p.s, (size_t)total_scratch, &w))) return rc;
+  if ((rc = get_workspace(p.dev, p.s, total_scratch, &w))) return rc;
   if ((rc = ensure_ev_staging(w, n_events, p.s))) return rc;
   if ((rc = ensure_counters(w, n_events, p.s))) return rc;
   const uint64_t cells = n_cells(*grid);
@@ -913,6 +934,26 @@ int ht_debug_unary(const float* v, float* root, float* inv2, int64_t n, void* st
   if (pointer_kind(v) == 0 || pointer_kind(root) == 0 || pointer_kind(inv2) == 0)
     return fail(HT_EINVAL, "an array is not device-accessible memory");
   return check_launch(launch_debug_unary(v, root, inv2, n, (hipStream_t)stream), "debug launch");
+}
+
+int ht_debug_batch_plan(const ht_grid* grid, const ht_event* events, int32_t n_events,
+                        int32_t* direct, int64_t* scratch_bytes)
+{
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (!events || !direct || !scratch_bytes || n_events < 1 || n_events > 65535)
+    return fail(HT_EINVAL, "invalid batch-plan arguments");
+  for (int32_t i = 0; i < n_events; ++i)
+    if (events[i].n_hits < 0 || events[i].n_hits > ((int64_t)1 << 28))
+      return fail(HT_EINVAL, "event %d has an invalid size", i);
+  // the tiling alone decides the layout; the tables (device memory) are not needed
+  const DevGrid g = make_devgrid(*grid, DevTables(), choose_tiling(*grid));
+  std::vector<size_t> offs;
+  size_t total = 0;
+  int64_t max_hits = 0;
+  *direct = plan_batch(g, events, n_events, &offs, &total, &max_hits) ? 1 : 0;
+  *scratch_bytes = (int64_t)total;
+  return HT_OK;
 }
 
 int ht_profile_enable(int mode)

@@ -29,6 +29,8 @@ constexpr uint32_t kTileOverflow = 0xffffffffu;
 // Direct slab lists (one fixed-capacity list per slab, capacity = the event's hit count) are
 // used while they need at most this many bytes per event; above it, a counting sort.
 constexpr size_t kDirectListMax = (size_t)1 << 29;
+// A batch uses direct lists only while the scratch of all its events stays within this.
+constexpr size_t kBatchDirectMax = (size_t)8 << 30;
 
 // Grid constants and tables as the kernels see them (passed by value as a kernel argument).
 struct DevGrid {
@@ -48,6 +50,7 @@ struct DevGrid {
   int32_t fill_tiles;      // fill tiles per workgroup (filled in turn)
   int32_t pool_bound;      // 1: large events get a candidate pool sized by their vote bound
   int32_t phi_sectors;     // 1: phi cells are independent sectors (no phi widening or neighbours)
+  int32_t packed_lists;    // 1: always the counting-sort (packed) slab lists, never direct ones
   int32_t test_blocks;     // workgroups per event of the candidate test
   const float* a2;         // device [n_a]
   const float* phi_cs;     // device [2 * 2 n_phi] (cos, sin)

@@ -58,24 +58,28 @@ def _refine(results, key, time_one, top=3, rounds=5):
         r["rounds"] = rounds
 
 
-def _run(spec, hits, acc, out, nf, cap, reps):
+def _run(spec, hits, accs, out, nf, cap, reps):
     import torch
-    for x, y, z in hits:
-        B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+    for k, (x, y, z) in enumerate(hits):
+        B.ht_fill_peaks(spec, x, y, z, accs[k % len(accs)], out, cap, nf)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(reps):
         x, y, z = hits[k % len(hits)]
-        B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+        B.ht_fill_peaks(spec, x, y, z, accs[k % len(accs)], out, cap, nf)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps
 
 
-def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool = True):
-    """Time every candidate on `events` (host (x, y, z) tuples); returns a report dict."""
+def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool = True,
+             n_acc: int = 1):
+    """Time every candidate on `events` (host (x, y, z) tuples), the calls cycling over n_acc
+    vote matrices (several matrices keep a single one from living in the last-level cache);
+    returns a report dict."""
     import torch
     hits = [B.hits_to_device(*e) for e in events]
-    acc = B.new_acc(spec)
+    accs = [B.new_acc(spec) for _ in range(max(1, n_acc))]
+    acc = accs[0]
     out, nf = B.new_peaks(capacity)
     B.ht_set_tuning(spec)
     # reference results: default shape
@@ -84,7 +88,7 @@ def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool 
         B.ht_fill_peaks(spec, x, y, z, acc, out, capacity, nf)
         torch.cuda.synchronize()
         ref.append((acc.clone(), B.peaks_to_host(out, nf, capacity)))
-    t_default = _run(spec, hits, acc, out, nf, capacity, reps)
+    t_default = _run(spec, hits, accs, out, nf, capacity, reps)
     results = []
 
     def trial(cand):
@@ -102,7 +106,7 @@ def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool 
                     and np.array_equal(pk[1], rpk[1])):
                 exact = False
                 break
-        t = _run(spec, hits, acc, out, nf, capacity, reps) if exact else None
+        t = _run(spec, hits, accs, out, nf, capacity, reps) if exact else None
         r = {"tuning": cand.as_dict(), "us_per_event": None if t is None else t * 1e6,
              "bit_exact": exact}
         results.append(r)
@@ -119,7 +123,7 @@ def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool 
 
     def time_one(tuning):
         B.ht_set_tuning(spec, B.Tuning(**tuning))
-        return _run(spec, hits, acc, out, nf, capacity, 3 * reps) * 1e6
+        return _run(spec, hits, accs, out, nf, capacity, 3 * reps) * 1e6
 
     _refine(results, "us_per_event", time_one)
     B.ht_set_tuning(spec)
@@ -127,9 +131,10 @@ def autotune(spec, events, reps: int = 30, capacity: int = 1 << 17, apply: bool 
     best = min(ok, key=lambda r: r["us_per_event"]) if ok else None
     if apply and best:
         B.ht_set_tuning(spec, B.Tuning(**best["tuning"]))
-    del acc, out, ref
+    del acc, accs, out, ref
     torch.cuda.empty_cache()
     return {"grid": grid_key(spec), "arch": arch_name(), "default_us_per_event": t_default * 1e6,
+            "matrices": max(1, n_acc),
             "best": best, "candidates": results}
 
 

@@ -16,9 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 @pytest.fixture(scope="module")
 def lib():
-    if not os.path.exists(B.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
+    from paper_1507_03074_amd import build as hbuild
+    hbuild.ensure_built()  # a missing or stale library is rebuilt, never tested
     return B.lib()
 
 
@@ -182,3 +181,28 @@ def test_sector_grids_validated_on_host(lib):
         oa2, oinv, ouphi, outh = oracle.tables(oracle.OracleGrid(*spec.as_tuple()))
         assert a2.tobytes() == oa2.tobytes() and uphi.tobytes() == ouphi.tobytes()
         assert B.ht_tiling(spec)["n_tiles"] >= 3 * n_phi
+
+
+def test_batch_plan_on_host(lib, monkeypatch):
+    """The slab-list layout of a batch, decided on the host before any device work: direct lists
+    for the 100-event batch of up to 8000 hits on the paper grid, the counting sort for the
+    16-event batch of 105600-hit events on the 8x32x2048x2048 grid (direct lists would need about
+    0.73 GB per event, past 8 GiB in all), and the counting sort everywhere under
+    HT_PACKED_LISTS=1."""
+    cfg1, cfg4 = synth.WORKLOADS[1].grid, synth.WORKLOADS[4].grid
+    direct, scratch = B.ht_debug_batch_plan(cfg1, [1000 + 70 * i for i in range(100)])
+    assert direct and scratch > 0
+    direct, scratch = B.ht_debug_batch_plan(cfg4, [105600] * 16)
+    assert not direct
+    one_direct, one_bytes = B.ht_debug_batch_plan(cfg4, [105600])
+    assert one_direct and 16 * one_bytes > 8 << 30
+    monkeypatch.setenv("HT_PACKED_LISTS", "1")
+    assert B.ht_debug_batch_plan(cfg1, [5000])[0] is False
+    monkeypatch.delenv("HT_PACKED_LISTS")
+    assert B.ht_debug_batch_plan(cfg1, [5000])[0] is True
+    # validation
+    g = B.make_grid(cfg1)
+    d, b = ctypes.c_int32(), ctypes.c_int64()
+    ev = (B.Event * 1)(B.Event(0, -1, 0, 0))
+    assert lib.ht_debug_batch_plan(ctypes.byref(g), ev, 1, ctypes.byref(d), ctypes.byref(b)) == B.HT_EINVAL
+    assert lib.ht_debug_batch_plan(ctypes.byref(g), ev, 0, ctypes.byref(d), ctypes.byref(b)) == B.HT_EINVAL

@@ -28,9 +28,8 @@ def say(*a):
 def gpu():
     import torch
     from paper_1507_03074_amd import binding as B
-    if not os.path.exists(B.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
+    from paper_1507_03074_amd import build as hbuild
+    hbuild.ensure_built()  # a missing or stale library is rebuilt, never tested
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     torch.cuda.set_device(0)
     B.lib()
@@ -310,8 +309,12 @@ def test_empty_and_degenerate_events(gpu):
     out, nf = B.new_peaks(2)
     B.ht_fill_peaks(CFG0, xd, yd, zd, acc, out, 2, nf)
     torch.cuda.synchronize()
-    c, v, n = B.peaks_to_host(out, nf, 2)
+    c, v, n = B.peaks_to_host(out, nf, 2, allow_truncation=True)
     assert n == on and np.array_equal(c, oc[:2]) and np.array_equal(v, ov[:2])
+    # the wrapper refuses a truncated list unless asked for one
+    with pytest.raises(B.HTError) as err:
+        B.peaks_to_host(out, nf, 2)
+    assert err.value.code == B.HT_EOVERFLOW
     # threshold above every count
     spec = synth.GridSpec(4, 16, 64, 64, threshold=10 ** 6)
     gM, gc, gv, gn = gpu_fused(B, spec, ev.x, ev.y, ev.z)

@@ -29,9 +29,8 @@ def B():
     import os
     import torch
     from paper_1507_03074_amd import binding as B
-    if not os.path.exists(B.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
+    from paper_1507_03074_amd import build as hbuild
+    hbuild.ensure_built()  # a missing or stale library is rebuilt, never tested
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     torch.cuda.set_device(0)
     B.lib()

@@ -17,35 +17,43 @@ from paper_1507_03074_amd import binding as B
 LLVM = "/opt/rocm/llvm/bin"
 FUSED_F32 = re.compile(r"\bv_(pk_)?(fma|fmac|mac|mad)(_mix\w*|_f32|_legacy_f32)\w*")
 PACKED_F32 = re.compile(r"\bv_pk_(add|mul|fma|mov)_f32\b")
+MAGIC = b"__CLANG_OFFLOAD_BUNDLE__"
 
 
 @pytest.fixture(scope="module")
 def disasm(tmp_path_factory):
-    if not os.path.exists(B.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
+    from paper_1507_03074_amd import build as hbuild
+    hbuild.ensure_built()  # a missing or stale library is rebuilt, never tested
     tools = [shutil.which("objcopy"), os.path.join(LLVM, "clang-offload-bundler"),
              os.path.join(LLVM, "llvm-objdump")]
     if not all(t and os.path.exists(t) for t in tools):
         pytest.skip("objcopy / ROCm LLVM tools not available")
     d = tmp_path_factory.mktemp("isa")
-    fat, co, scratch = str(d / "fatbin"), str(d / "gfx950.co"), str(d / "copy.so")
+    fat, scratch = str(d / "fatbin"), str(d / "copy.so")
     # with no output file objcopy would rewrite the library in place, under this process's
     # own mapping of it: the rewritten copy goes to the scratch file instead
     subprocess.check_call([tools[0], "--dump-section", ".hip_fatbin=" + fat, B.LIB_PATH, scratch])
-    subprocess.check_call([tools[1], "--unbundle", "--type=o",
-                           "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--input=" + fat,
-                           "--output=" + co])
-    text = subprocess.check_output([tools[2], "-d", "--no-show-raw-insn", co], text=True)
+    # one offload bundle per HIP translation unit, concatenated by the linker
+    data = open(fat, "rb").read()
+    starts = [m.start() for m in re.finditer(re.escape(MAGIC), data)]
+    assert starts, "no offload bundle in the library"
     kernels = collections.defaultdict(list)
-    cur = None
-    for line in text.splitlines():
-        m = re.match(r"^[0-9a-f]+ <(.+)>:$", line)
-        if m:
-            cur = m.group(1)
-            continue
-        if cur and line.strip():
-            kernels[cur].append(line.strip())
+    for k, a in enumerate(starts):
+        part, co = str(d / ("bundle%d" % k)), str(d / ("gfx950_%d.co" % k))
+        with open(part, "wb") as f:
+            f.write(data[a:starts[k + 1] if k + 1 < len(starts) else len(data)])
+        subprocess.check_call([tools[1], "--unbundle", "--type=o",
+                               "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--input=" + part,
+                               "--output=" + co])
+        text = subprocess.check_output([tools[2], "-d", "--no-show-raw-insn", co], text=True)
+        cur = None
+        for line in text.splitlines():
+            m = re.match(r"^[0-9a-f]+ <(.+)>:$", line)
+            if m:
+                cur = m.group(1)
+                continue
+            if cur and line.strip():
+                kernels[cur].append(line.strip())
     return kernels
 
 
