@@ -28,6 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # for the library's default of a field), measured fastest on MI355X with the matrices cycled;
 # the committed profiles are taken at it.
 PINNED_TUNING = "4,16,0,1,1"
+# Launch shapes the batch autotuner picks for the batched (workload 2) and stress (workload 4)
+# batches on MI355X; --only pins them, so that a profiled run times no search.
+BATCH_TUNING = {"batched": "4,16,256,1,2", "stress": "4,16,256,1,8"}
 
 
 def log(*a):
@@ -574,6 +577,12 @@ def main():
     ap.add_argument("--crowded", action="store_true",
                     help="stage times on small, median and crowded events of the served stream "
                          "(workload 3) at the --tuning shape or the default; prints one line")
+    ap.add_argument("--only", choices=("batched", "stress", "served"),
+                    help="one workload only, for profiles: the batched workload 2 (100 events, "
+                         "one graph launch) or the stress workload 4 (16 events) at the launch "
+                         "shape the batch autotuner picks, --steps capped at 10 batches; or the "
+                         "served workload 3 at its saturation rate on a short trace; prints one "
+                         "line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path. Events are "
@@ -592,6 +601,18 @@ def main():
         tuning = None if args.tuning == PINNED_TUNING else args.tuning
         print(json.dumps({"crowded": bench_crowded(B, torch, synth, min(args.steps, 50), tuning)}),
               flush=True)
+        return
+    if args.only in ("batched", "stress"):
+        wl, n_ev, cap_b = (2, 100, 1 << 13) if args.only == "batched" else (4, 16, 1 << 21)
+        B.ht_set_tuning(synth.WORKLOADS[wl].grid, B.Tuning(*pinned_tuning(BATCH_TUNING[args.only])))
+        res = bench_batched(B, torch, synth, wl, n_ev, min(args.steps, 10), cap_b)
+        print(json.dumps({args.only: res}), flush=True)
+        return
+    if args.only == "served":
+        B.ht_set_tuning(synth.WORKLOADS[3].grid, B.Tuning(*pinned_tuning(args.tuning)))
+        res = bench_served(B, torch, synth, n_pool=64, n_warm=50, n_meas=300, rates=(1.0,),
+                           budget_gib=24, max_batch=8, n_streams=2)
+        print(json.dumps({"served": res}), flush=True)
         return
     workload = 1
     spec = synth.WORKLOADS[workload].grid

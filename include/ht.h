@@ -210,7 +210,8 @@ typedef struct ht_serve_opts {
   int64_t max_hits;           /* largest event accepted (> 0) */
   int32_t max_batch;          /* events per launched batch (>= 1) */
   int32_t n_streams;          /* device streams used for overlapping batches (>= 1) */
-  int32_t queue_depth;        /* submitted-but-not-polled requests accepted (>= 1) */
+  int32_t queue_depth;        /* requests submitted and not yet completed (>= 1); each holds
+                                 a pinned staging buffer of max_hits hits until it completes */
   int32_t device;             /* HIP device ordinal */
 } ht_serve_opts;
 
@@ -227,7 +228,8 @@ int ht_serve_create(const ht_grid* grid, const ht_serve_opts* opts, ht_server** 
 
 /* ht_serve_submit: HOST x, y, z[n_hits]; copied into the server's pinned staging before the
  * call returns (the caller may reuse its buffers at once). *ticket identifies the request.
- * Errors: HT_EINVAL (n_hits < 0 or > max_hits), HT_EAGAIN (queue_depth requests outstanding). */
+ * Errors: HT_EINVAL (n_hits < 0 or > max_hits), HT_EAGAIN (queue_depth requests submitted and
+ * not yet completed: retry after some complete). */
 int ht_serve_submit(ht_server* server, const float* x, const float* y, const float* z,
                     int64_t n_hits, uint64_t* ticket);
 

@@ -63,21 +63,17 @@ int validate_grid(const ht_grid* g)
 uint64_t n_cells(const ht_grid& g) { return (uint64_t)g.n_theta * g.n_phi * g.n_a * g.n_b; }
 
 // Bin-rule tables, computed in double and rounded once to float.
-void host_tables(const ht_grid& g, std::vector<float>& a2, float& inv_db, std::vector<float>& phi,
-                 std::vector<float>& th)
+void host_tables_into(const ht_grid& g, float* a2, float* inv_db, float* phi, float* th)
 {
-  a2.resize(g.n_a);
   const double da = ((double)g.a_max - (double)g.a_min) / (double)g.n_a;
   for (int32_t i = 0; i < g.n_a; ++i)
     a2[i] = (float)(2.0 * (double)g.a_min + (double)(2 * (int64_t)i + 1) * da);
-  inv_db = (float)((double)g.n_b / ((double)g.b_max - (double)g.b_min));
-  phi.resize(4 * (size_t)g.n_phi);
+  *inv_db = (float)((double)g.n_b / ((double)g.b_max - (double)g.b_min));
   for (int32_t m = 0; m < 2 * g.n_phi; ++m) {
     const double ang = ((double)m * kPi) / (double)g.n_phi;
     phi[2 * m] = (float)std::cos(ang);
     phi[2 * m + 1] = (float)std::sin(ang);
   }
-  th.resize(2 * (2 * (size_t)g.n_theta + 1));
   for (int32_t m = 0; m <= 2 * g.n_theta; ++m) {
     const double ang = ((double)m * kPi) / (double)(2 * g.n_theta);
     th[2 * m] = (float)std::cos(ang);
@@ -85,15 +81,18 @@ void host_tables(const ht_grid& g, std::vector<float>& a2, float& inv_db, std::v
   }
 }
 
+void host_tables(const ht_grid& g, std::vector<float>& a2, float& inv_db, std::vector<float>& phi,
+                 std::vector<float>& th)
+{
+  a2.resize(a2_floats(g));
+  phi.resize(phi_floats(g));
+  th.resize(th_floats(g));
+  host_tables_into(g, a2.data(), &inv_db, phi.data(), th.data());
+}
+
 // ---------------------------------------------------------------------------------------------
 // Tiling
 // ---------------------------------------------------------------------------------------------
-struct Tiling {
-  int32_t rows, tiles_per_slab, n_tiles, cand_cap, lds_fill, group_tiles, nt_store, fill_tiles;
-  int32_t pool_bound;
-  int32_t packed_lists;
-};
-
 static int env_int(const char* name, int def)
 {
   const char* v = std::getenv(name);
@@ -209,13 +208,6 @@ int check_tuning(const ht_grid& g, const ht_tuning& tu)
 // ---------------------------------------------------------------------------------------------
 // Device tables, cached per (device, grid)
 // ---------------------------------------------------------------------------------------------
-struct DevTables {
-  float* a2 = nullptr;
-  float* phi = nullptr;
-  float* th = nullptr;
-  float inv_db = 0.0f;
-};
-
 static std::mutex g_mu;
 typedef std::tuple<int, int32_t, int32_t, int32_t, int32_t, uint32_t, uint32_t, uint32_t, uint32_t>
     TabKey;
@@ -512,6 +504,7 @@ struct StageTimer {
   hipEvent_t a = nullptr;
   StageTimer(const char* n, hipStream_t st) : name(n), s(st)
   {
+    if (!name) return;  // untimed call
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (g_prof_mode == 0 || t_capturing) return;
     if (g_prof_mode == 2 && std::strncmp(name, "fill", 4) != 0) return;
@@ -552,17 +545,32 @@ int check_launch(hipError_t e, const char* what)
   return HT_OK;
 }
 
+// Failure injection for tests of the error paths: with HT_TEST_FAIL_STAGE set to a stage name
+// ("prep", "fill" or "peaks"), that stage's launch is not made and the call fails as a failed
+// launch would (HT_EDEVICE), with the earlier stages already on the stream.
+int injected_failure(const char* stage)
+{
+  const char* v = std::getenv("HT_TEST_FAIL_STAGE");
+  if (v && std::strcmp(v, stage) == 0)
+    return fail(HT_EDEVICE, "injected failure before the %s launch (HT_TEST_FAIL_STAGE)", stage);
+  return HT_OK;
+}
+
 int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, bool direct,
-                 hipStream_t s)
+                 hipStream_t s, bool* prep_enqueued)
 {
   EvDesc none;
   std::memset(&none, 0, sizeof(none));
   int rc;
+  *prep_enqueued = false;
   {
     StageTimer t("prep", s);
-    if ((rc = check_launch(launch_prep(g, none, d_ev, n_ev, max_hits, direct && g.lds_fill, s), "prep launch")))
+    if ((rc = injected_failure("prep")) ||
+        (rc = check_launch(launch_prep(g, none, d_ev, n_ev, max_hits, direct && g.lds_fill, s), "prep launch")))
       return rc;
+    *prep_enqueued = true;
   }
+  if ((rc = injected_failure("fill"))) return rc;
   if (g.lds_fill) {
     StageTimer t("fill", s);
     if ((rc = check_launch(launch_fill(g, none, d_ev, n_ev, true, max_hits, s), "fill launch"))) return rc;
@@ -575,6 +583,7 @@ int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hit
     StageTimer t("candidates", s);
     if ((rc = check_launch(launch_candidates(g, none, d_ev, n_ev, s), "candidate launch"))) return rc;
   }
+  if ((rc = injected_failure("peaks"))) return rc;
   StageTimer t("peaks", s);
   return check_launch(launch_peaks(g, none, d_ev, n_ev, s), "peak launch");
 }
@@ -634,6 +643,44 @@ bool plan_batch(const DevGrid& g, const ht_event* events, int n_events, std::vec
   return direct;
 }
 
+int enqueue_event(const DevGrid& g, const EvDesc& ev, int64_t nh, bool direct, bool atomic,
+                  bool do_fill, bool do_peaks, bool timed, hipStream_t s, bool* counters_used)
+{
+  // stage timers only where asked for (they may create HIP events); a null name times nothing
+#define HT_STAGE(var, name) StageTimer var(timed ? name : nullptr, s)
+  int rc;
+  *counters_used = false;
+  if (do_fill) {
+    {
+      HT_STAGE(t, "prep");
+      if ((rc = injected_failure("prep")) ||
+          (rc = check_launch(launch_prep(g, ev, nullptr, 1, nh, direct, s), "prep launch")))
+        return rc;
+      *counters_used = true;
+    }
+    if ((rc = injected_failure("fill"))) return rc;
+    if (atomic) {
+      HT_STAGE(t, "fill_atomic");
+      if ((rc = check_launch(launch_fill_atomic(g, ev, nullptr, 1, nh, s), "fill launch"))) return rc;
+    } else {
+      HT_STAGE(t, "fill");
+      if ((rc = check_launch(launch_fill(g, ev, nullptr, 1, do_peaks, nh, s), "fill launch"))) return rc;
+    }
+  }
+  if (do_peaks) {
+    if (!do_fill || atomic) {
+      HT_STAGE(t, "candidates");
+      if ((rc = check_launch(launch_candidates(g, ev, nullptr, 1, s), "candidate launch"))) return rc;
+      *counters_used = true;
+    }
+    if ((rc = injected_failure("peaks"))) return rc;
+    HT_STAGE(t, "peaks");
+    if ((rc = check_launch(launch_peaks(g, ev, nullptr, 1, s), "peak launch"))) return rc;
+  }
+#undef HT_STAGE
+  return HT_OK;
+}
+
 int run_event(const ht_grid* grid, const float* x, const float* y, const float* z, int64_t n,
               uint32_t* acc, ht_peak* out, int64_t cap, int64_t* n_found, void* stream,
               bool do_fill, bool do_peaks, bool force_atomic)
@@ -667,32 +714,12 @@ int run_event(const ht_grid* grid, const float* x, const float* y, const float* 
   ev.out = out;
   ev.cap = cap;
   ev.n_found = n_found;
-  if (do_fill) {
-    {
-      StageTimer t("prep", p.s);
-      rc = check_launch(launch_prep(p.g, ev, nullptr, 1, nh, direct, p.s), "prep launch");
-      flip_counters(w, 1);
-      if (rc) return rc;
-    }
-    if (atomic) {
-      StageTimer t("fill_atomic", p.s);
-      if ((rc = check_launch(launch_fill_atomic(p.g, ev, nullptr, 1, nh, p.s), "fill launch"))) return rc;
-    } else {
-      StageTimer t("fill", p.s);
-      if ((rc = check_launch(launch_fill(p.g, ev, nullptr, 1, do_peaks, nh, p.s), "fill launch"))) return rc;
-    }
-  }
-  if (do_peaks) {
-    if (!do_fill || atomic) {
-      StageTimer t("candidates", p.s);
-      rc = check_launch(launch_candidates(p.g, ev, nullptr, 1, p.s), "candidate launch");
-      if (!do_fill) flip_counters(w, 1);
-      if (rc) return rc;
-    }
-    StageTimer t("peaks", p.s);
-    if ((rc = check_launch(launch_peaks(p.g, ev, nullptr, 1, p.s), "peak launch"))) return rc;
-  }
-  return HT_OK;
+  bool used = false;
+  rc = enqueue_event(p.g, ev, nh, direct, atomic, do_fill, do_peaks, true, p.s, &used);
+  // the next call counts into the other array only if a kernel of this call counts into this
+  // one and clears that one (a launch that failed before it leaves both as they were)
+  if (used) flip_counters(w, 1);
+  return rc;
 }
 
 }  // namespace ht
@@ -706,13 +733,7 @@ int ht_tables(const ht_grid* grid, float* a2, float* inv_db, float* phi_cs, floa
   int rc = validate_grid(grid);
   if (rc) return rc;
   if (!a2 || !inv_db || !phi_cs || !th_cs) return fail(HT_EINVAL, "table pointers are NULL");
-  std::vector<float> va2, vphi, vth;
-  float inv;
-  host_tables(*grid, va2, inv, vphi, vth);
-  std::memcpy(a2, va2.data(), va2.size() * 4);
-  *inv_db = inv;
-  std::memcpy(phi_cs, vphi.data(), vphi.size() * 4);
-  std::memcpy(th_cs, vth.data(), vth.size() * 4);
+  host_tables_into(*grid, a2, inv_db, phi_cs, th_cs);
   return HT_OK;
 }
 
@@ -805,12 +826,17 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
   while (blocks * 256 < max_hits) blocks *= 2;
   const int64_t max_hits_b = max_hits > 0 ? blocks * 256 : 0;
   hipError_t e;
-  flip_counters(w, n_events);  // the descriptors above hold this call's counter arrays
+  // The descriptors above hold this call's counter arrays. The next call switches to the other
+  // arrays only once this call's preparation (which counts into these and clears those) is on
+  // the stream; a call that fails before that leaves the counters as they were.
   if (env_int("HT_BATCH_GRAPH", 1) == 0) {
     e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, p.s);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(descriptors)");
     if ((e = hipEventRecord(w->ev_copied, p.s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
-    return launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, p.s);
+    bool prep_enqueued = false;
+    rc = launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, p.s, &prep_enqueued);
+    if (prep_enqueued) flip_counters(w, n_events);
+    return rc;
   }
   // graph key: everything the captured launches depend on besides the descriptor contents
   std::vector<unsigned char> key(sizeof(DevGrid) + 4 * sizeof(int64_t) + 2 * sizeof(void*));
@@ -836,8 +862,10 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
       return fail_hip(e, "hipStreamBeginCapture");
     t_capturing = true;
     e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, w->capture);
-    int lrc = e == hipSuccess ? launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, w->capture)
-                              : HT_EDEVICE;
+    bool captured_prep = false;
+    int lrc = e == hipSuccess
+                  ? launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, w->capture, &captured_prep)
+                  : HT_EDEVICE;
     t_capturing = false;
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(w->capture, &graph);
@@ -860,6 +888,7 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
     StageTimer t("batch", p.s);
     if ((e = hipGraphLaunch(exec, p.s)) != hipSuccess) return fail_hip(e, "hipGraphLaunch");
   }
+  flip_counters(w, n_events);
   if ((e = hipEventRecord(w->ev_copied, p.s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
   return HT_OK;
 }

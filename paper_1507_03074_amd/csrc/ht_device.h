@@ -432,8 +432,6 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
   }
 }
 
-// Candidates of an arbitrary matrix: one coalesced read of each tile into LDS. Workgroup 0
-
 template <int ROWS, bool NT, int CACHE>
 hipError_t launch_fill_cache(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                              bool vec, bool emit, size_t lds, hipStream_t s)

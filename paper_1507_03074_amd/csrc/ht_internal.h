@@ -86,6 +86,30 @@ struct EvDesc {
   uint32_t* group_pk;   // [n_groups] peaks per group of tiles
 };
 
+// Launch shape of one grid (ht_tuning resolved against the defaults).
+struct Tiling {
+  int32_t rows, tiles_per_slab, n_tiles, cand_cap, lds_fill, group_tiles, nt_store, fill_tiles;
+  int32_t pool_bound;
+  int32_t packed_lists;
+};
+Tiling choose_tiling(const ht_grid& g);
+
+// Device copies of the bin-rule tables of one grid.
+struct DevTables {
+  float* a2 = nullptr;
+  float* phi = nullptr;
+  float* th = nullptr;
+  float inv_db = 0.0f;
+};
+// Floats of each table: a2[n_a], phi (cos, sin)[2 n_phi], theta (cos, sin)[2 n_theta + 1].
+inline size_t a2_floats(const ht_grid& g) { return (size_t)g.n_a; }
+inline size_t phi_floats(const ht_grid& g) { return 4 * (size_t)g.n_phi; }
+inline size_t th_floats(const ht_grid& g) { return 2 * (2 * (size_t)g.n_theta + 1); }
+// The tables computed on the host in double and rounded once to float, into caller arrays of
+// the sizes above.
+void host_tables_into(const ht_grid& g, float* a2, float* inv_db, float* phi, float* th);
+DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl);
+
 // Whether an event of n_hits hits uses direct slab lists (see kDirectListMax).
 bool direct_lists(const DevGrid& g, int64_t n_hits);
 // Bytes of per-event scratch for a grid tiling and an event size, and the carving of it.
@@ -114,6 +138,17 @@ size_t fill_lds_bytes(const DevGrid& g);
 int n_groups(const DevGrid& g);
 
 // Host helpers (ht_api.cpp).
+// 0: not usable by a kernel; 1: device memory; 2: pinned host memory mapped into the device;
+// 3: managed memory.
+int pointer_kind(const void* ptr);
+int check_accessible(const void* ptr, const char* what);
+// Enqueues one event's stages on s: prep (counting into ev.slab_cnt and clearing
+// ev.slab_cnt_next), then the fill, then the peak search, as do_fill / do_peaks ask; `atomic`
+// takes the global-atomic fill and a candidate scan of the matrix. *counters_used is set once
+// a kernel that uses the counter pair is on the stream (the caller then flips to the other
+// array for its next call). `timed` records the stage timers of ht_profile_enable.
+int enqueue_event(const DevGrid& g, const EvDesc& ev, int64_t n_hits, bool direct, bool atomic,
+                  bool do_fill, bool do_peaks, bool timed, hipStream_t s, bool* counters_used);
 int fail(int code, const char* fmt, ...);
 int fail_hip(hipError_t e, const char* what);
 int validate_grid(const ht_grid* g);
@@ -122,7 +157,9 @@ uint64_t n_cells(const ht_grid& g);
 int make_device_grid(const ht_grid& g, int dev, DevGrid* out);
 // The whole batched pipeline (prep, fill with candidates, peaks) for n_ev events whose
 // descriptors are already in device memory.
+// *prep_enqueued is set once the preparation (which counts into and clears the events' counter
+// arrays) is on the stream.
 int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, bool direct,
-                 hipStream_t s);
+                 hipStream_t s, bool* prep_enqueued);
 
 }  // namespace ht

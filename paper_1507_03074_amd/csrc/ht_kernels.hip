@@ -267,7 +267,10 @@ __global__ __launch_bounds__(kBlock) void k_bucket(DevGrid g, EvDesc ev0, const 
     e.list[s_off[s] + e.hit_pos[4 * h + q]] = rec;
   }
 }
-// clears the other counter array for the next call.
+
+// Candidates of an arbitrary matrix: one coalesced read of each tile into LDS, then the same
+// count and ordered emission as the fill's. Workgroup 0 clears the other counter array for the
+// next call.
 template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_cand_scan(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
@@ -396,6 +399,25 @@ __device__ __forceinline__ void tile_range(const DevGrid& g, int tile, uint32_t*
   *L = (uint32_t)rows * (uint32_t)g.n_b;
 }
 
+// Candidates of an arbitrary matrix whose B rows are too wide for an LDS tile (grids that also
+// fill through global atomics; a tile is then one row of up to 2^24 cells): the same count and
+// ordered emission as k_cand_scan, read straight from the matrix, so the row is read twice.
+// Workgroup 0 clears the other counter array for the next call.
+__global__ __launch_bounds__(kBlock) void k_cand_scan_wide(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  __shared__ uint32_t s_small[16];
+  EvDesc e = load_ev(ev0, evs);
+  const int tile = blockIdx.x;
+  if (tile == 0)
+    for (int i = threadIdx.x; i < kCounterWords; i += kBlock) gp(e.slab_cnt_next)[i] = 0u;
+  uint32_t cell0, L;
+  tile_range(g, tile, &cell0, &L);
+  const uint32_t* src = e.acc + cell0;
+  count_candidates<false>(src, L, g.threshold, s_small);
+  lds_barrier();
+  emit_candidates<false>(g, e, tile, cell0, src, L, s_small);
+}
+
 // Largest t with pre[t] <= f, given pre[0] <= f < pre[kGroupTiles] and pre non-decreasing: a
 // fixed number of halving steps, with no branch.
 __device__ __forceinline__ int group_tile_of(const uint32_t* pre, uint32_t f)
@@ -449,10 +471,11 @@ __device__ bool row_beats(const DevGrid& g, const uint32_t* __restrict__ acc, ui
 
 __device__ __forceinline__ void count_peak(const DevGrid& g, const EvDesc& e, uint32_t c)
 {
-  const uint32_t nb = (uint32_t)g.n_b;
-  const uint32_t slab_cells = (uint32_t)g.n_a * nb;
-  const uint32_t slab = c / slab_cells;
-  const uint32_t a = (c - slab * slab_cells) / nb;
+  // (slab, a) from the row index c / n_b: a slab of one cell row by 2^32 cells (n_a n_b = 2^32)
+  // would wrap a 32-bit slab size
+  const uint32_t row = c / (uint32_t)g.n_b;
+  const uint32_t slab = row / (uint32_t)g.n_a;
+  const uint32_t a = row - slab * (uint32_t)g.n_a;
   const uint32_t tile = slab * (uint32_t)g.tiles_per_slab + a / (uint32_t)g.rows;
   gatomic_add(e.tile_pk + tile, 1u);
   gatomic_add(e.group_pk + tile / (uint32_t)g.group_tiles, 1u);
@@ -812,8 +835,13 @@ hipError_t launch_fill(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, i
 hipError_t launch_candidates(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                              hipStream_t s)
 {
-  const size_t lds = fill_lds_bytes(g);
   dim3 grid(g.n_tiles, n_ev);
+  if (!g.lds_fill) {
+    // rows wider than an LDS tile (up to 2^24 cells): read from the matrix directly
+    hipLaunchKernelGGL(k_cand_scan_wide, grid, dim3(kBlock), 0, s, g, ev0, evs);
+    return hipGetLastError();
+  }
+  const size_t lds = fill_lds_bytes(g);
   if (g.n_b % 4 == 0) hipLaunchKernelGGL(k_cand_scan<true>, grid, dim3(kBlock), lds, s, g, ev0, evs);
   else hipLaunchKernelGGL(k_cand_scan<false>, grid, dim3(kBlock), lds, s, g, ev0, evs);
   return hipGetLastError();

@@ -136,7 +136,6 @@ int launch(ht_server* sv, Batch& b)
     carve_event_scratch(sv->g, mh, sv->direct, sl.scratch, &d);
     d.slab_cnt = sl.ctr + (sl.parity ? kCounterWords : 0);
     d.slab_cnt_next = sl.ctr + (sl.parity ? 0 : kCounterWords);
-    sl.parity ^= 1;
     d.x = sl.hits;
     d.y = sl.hits + r->n;
     d.z = sl.hits + 2 * r->n;
@@ -150,7 +149,13 @@ int launch(ht_server* sv, Batch& b)
   if ((e = hipMemcpyAsync(sv->d_ev[b.stream], sv->h_ev[b.stream], sizeof(EvDesc) * b.reqs.size(),
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail_hip(e, "hipMemcpyAsync(descriptors)");
-  int rc = launch_batch(sv->g, sv->d_ev[b.stream], (int)b.reqs.size(), max_n, sv->direct, s);
+  bool prep_enqueued = false;
+  int rc = launch_batch(sv->g, sv->d_ev[b.stream], (int)b.reqs.size(), max_n, sv->direct, s,
+                        &prep_enqueued);
+  // a slot switches counter arrays only once the preparation that counts into this one and
+  // clears the other is on the stream
+  if (prep_enqueued)
+    for (Request* r : b.reqs) sv->slots[r->slot].parity ^= 1;
   if (rc) return rc;
   if ((e = hipEventRecord(sv->done_ev[b.stream], s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
   return HT_OK;
