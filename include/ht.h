@@ -154,6 +154,27 @@ int ht_fill_peaks(const ht_grid* grid, const float* x, const float* y, const flo
                   int64_t n_hits, uint32_t* acc, ht_peak* out, int64_t capacity,
                   int64_t* n_found, void* stream);
 
+/* ht_fill_peaks_noalloc: ht_fill_peaks for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid hipMalloc). Same arguments
+ * and results as ht_fill_peaks (bit-identical matrix, peak list and count), but all of the
+ * library's scratch for the call (slab lists, candidate pool, counters, tables) lives in one
+ * fixed 64 MiB device array that each GPU the library runs on holds until the process ends;
+ * the call makes no hipMalloc, hipFree or other allocating call.
+ * Limits: n_a <= 16384, and the event's scratch must fit the array: direct slab lists are used
+ * while they fit, else the counting sort; about 25 MB for 5000 hits on the 4x16x1024x1024 grid,
+ * and a 40000-hit event still fits. A larger event is refused with HT_EINVAL before any device
+ * work, and ht_last_error() states the bytes it needed (use ht_fill_peaks for it).
+ * Sharing: every call on one GPU uses that GPU's array, which keeps the last call's contents.
+ * Calls on one GPU must not overlap (on different streams or host threads they race on the
+ * array); calls are serialised on the host by a lock, so overlap only arises from work still
+ * running on the device when a call on another stream starts. The first call with a grid whose
+ * tables differ from the last one's uploads the tables with a synchronous copy on `stream`, so
+ * make that first call outside any graph capture.
+ * Errors: as ht_fill_peaks. */
+int ht_fill_peaks_noalloc(const ht_grid* grid, const float* x, const float* y, const float* z,
+                          int64_t n_hits, uint32_t* acc, ht_peak* out, int64_t capacity,
+                          int64_t* n_found, void* stream);
+
 /* Track parameters of one peak (paper section 2: the centre (A, B) of the circle gives
  * rho = sqrt(A^2 + B^2) and phi = tan^-1(B/A)). */
 typedef struct ht_track {

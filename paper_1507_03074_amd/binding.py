@@ -86,6 +86,7 @@ class Timing(ctypes.Structure):
 
 #: every symbol the public headers declare
 EXPORTS = ["ht_set_tuning", "ht_get_tuning", "ht_tables", "ht_fill", "ht_peaks", "ht_fill_peaks", "ht_fill_peaks_batch",
+           "ht_fill_peaks_noalloc",
            "ht_serve_create", "ht_serve_submit", "ht_serve_poll", "ht_serve_destroy",
            "ht_last_error", "ht_debug_hit_values", "ht_debug_unary", "ht_fill_atomic", "ht_tiling",
            "ht_profile_enable", "ht_profile_read", "ht_bench_hbm_write", "ht_bench_hbm_read",
@@ -117,6 +118,7 @@ def lib():
         "ht_fill_atomic": ([gp, vp, vp, vp, i64, vp, vp], ctypes.c_int),
         "ht_peaks": ([gp, vp, vp, i64, vp, vp], ctypes.c_int),
         "ht_fill_peaks": ([gp, vp, vp, vp, i64, vp, vp, i64, vp, vp], ctypes.c_int),
+        "ht_fill_peaks_noalloc": ([gp, vp, vp, vp, i64, vp, vp, i64, vp, vp], ctypes.c_int),
         "ht_fill_peaks_batch": ([gp, ctypes.POINTER(Event), i32, vp, vp, vp, vp, vp, vp, vp],
                                 ctypes.c_int),
         "ht_debug_hit_values": ([gp, vp, vp, vp, i64, vp, vp, vp, vp], ctypes.c_int),
@@ -266,6 +268,15 @@ def ht_fill_peaks(spec, x, y, z, acc, out, capacity, n_found, stream=None):
     return check(lib().ht_fill_peaks(ctypes.byref(g), _ptr(x), _ptr(y), _ptr(z), x.numel(),
                                      _ptr(acc), _ptr(out), capacity, _ptr(n_found),
                                      _stream(stream)))
+
+
+def ht_fill_peaks_noalloc(spec, x, y, z, acc, out, capacity, n_found, stream=None):
+    g = make_grid(spec)
+    _need_cuda(x, y, z, acc)
+    _need_out(out, n_found)
+    return check(lib().ht_fill_peaks_noalloc(ctypes.byref(g), _ptr(x), _ptr(y), _ptr(z), x.numel(),
+                                             _ptr(acc), _ptr(out), capacity, _ptr(n_found),
+                                             _stream(stream)))
 
 
 def ht_fill_peaks_batch(spec, events, x, y, z, acc, out, n_found, stream=None):

@@ -23,7 +23,8 @@ LIB = os.path.join(PKG, "libht.so")
 
 FILL_ROWS = (1, 2, 4, 8, 16, 32, 64)
 # (source, extra defines) of every object
-UNITS = ([("ht_kernels.hip", []), ("ht_api.cpp", []), ("ht_serve.cpp", []), ("ht_roofline.hip", [])] +
+UNITS = ([("ht_kernels.hip", []), ("ht_api.cpp", []), ("ht_serve.cpp", []), ("ht_roofline.hip", []),
+          ("ht_noalloc.hip", [])] +
          [("ht_fill_rows.hip", ["-DHT_FILL_ROWS=%d" % r]) for r in FILL_ROWS])
 
 # -ffp-contract=off: the bin rule is one rounding per operation, never a fused multiply-add.

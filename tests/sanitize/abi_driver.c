@@ -135,6 +135,12 @@ int main(void)
   EXPECT_EINVAL(ht_peaks(&small, acc, NULL, 4, nf, NULL));
   EXPECT_EINVAL(ht_peaks(&small, acc, out, 4, NULL, NULL));
   EXPECT_EINVAL(ht_fill_peaks(&small, dummy, dummy, dummy, -1, acc, out, 4, nf, NULL));
+  EXPECT_EINVAL(ht_fill_peaks_noalloc(&small, dummy, dummy, dummy, -1, acc, out, 4, nf, NULL));
+  EXPECT_EINVAL(ht_fill_peaks_noalloc(&small, dummy, dummy, dummy, 4, NULL, out, 4, nf, NULL));
+  EXPECT_EINVAL(ht_fill_peaks_noalloc(&small, dummy, dummy, dummy, 4, acc, out, -1, nf, NULL));
+  ht_grid many_a = small;
+  many_a.n_a = 32768;
+  EXPECT_EINVAL(ht_fill_peaks_noalloc(&many_a, dummy, dummy, dummy, 4, acc, out, 4, nf, NULL));
   EXPECT_EINVAL(ht_fill_peaks_batch(&small, evs, -1, dummy, dummy, dummy, acc, out, nf, NULL));
   EXPECT_EINVAL(ht_fill_peaks_batch(&small, evs, 65536, dummy, dummy, dummy, acc, out, nf, NULL));
   EXPECT_EINVAL(ht_fill_peaks_batch(&small, NULL, 1, dummy, dummy, dummy, acc, out, nf, NULL));
