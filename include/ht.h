@@ -113,6 +113,12 @@ typedef struct ht_tuning {
                            stores */
   int32_t tiles_per_block; /* fill tiles per workgroup, filled in turn with one LDS tile (the
                               slab's hit records are read once): a power of two <= 64 */
+  int32_t dense_hits;   /* crowded events: a fused fill + peak search of an event with at least
+                           this many hits finds its peaks with a stencil over the whole matrix
+                           (one read of it, cost independent of the number of candidates)
+                           instead of the candidate pool; -1 never. The stencil needs LDS
+                           fill tiles, at most 512 (theta, phi) cells and n_b a multiple of 8;
+                           ht_get_tuning reports -1 where it is unavailable. */
 } ht_tuning;
 
 /* ht_set_tuning: use `tuning` for every later call on grids with these dimensions and ranges
@@ -162,8 +168,9 @@ int ht_fill_peaks(const ht_grid* grid, const float* x, const float* y, const flo
  * the call makes no hipMalloc, hipFree or other allocating call.
  * Limits: n_a <= 16384, and the event's scratch must fit the array: direct slab lists are used
  * while they fit, else the counting sort; about 25 MB for 5000 hits on the 4x16x1024x1024 grid,
- * and a 40000-hit event still fits. A larger event is refused with HT_EINVAL before any device
- * work, and ht_last_error() states the bytes it needed (use ht_fill_peaks for it).
+ * where events of up to about 500 000 hits fit (crowded events need no candidate pool). A larger
+ * event is refused with HT_EINVAL before any device work, and ht_last_error() states the bytes
+ * it needed (use ht_fill_peaks for it).
  * Sharing: every call on one GPU uses that GPU's array, which keeps the last call's contents.
  * Calls on one GPU must not overlap (on different streams or host threads they race on the
  * array); calls are serialised on the host by a lock, so overlap only arises from work still

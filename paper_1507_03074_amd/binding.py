@@ -73,7 +73,7 @@ class ServeOpts(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("group_tiles", ctypes.c_int32),
                 ("cand_cap", ctypes.c_int32), ("nt_store", ctypes.c_int32),
-                ("tiles_per_block", ctypes.c_int32)]
+                ("tiles_per_block", ctypes.c_int32), ("dense_hits", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -215,18 +215,19 @@ def ht_tables(spec):
 
 def ht_set_tuning(spec, tuning=None, **fields):
     """Set the launch shape for a grid (a Tuning, or fields rows/group_tiles/cand_cap/nt_store/
-    tiles_per_block; unspecified fields keep the default). ht_set_tuning(spec) restores the
-    defaults."""
+    tiles_per_block/dense_hits; unspecified fields keep the default). ht_set_tuning(spec)
+    restores the defaults."""
     g = make_grid(spec)
     if tuning is None and not fields:
         return check(lib().ht_set_tuning(ctypes.byref(g), None))
     if tuning is None:
-        unknown = set(fields) - {"rows", "group_tiles", "cand_cap", "nt_store", "tiles_per_block"}
+        unknown = set(fields) - {"rows", "group_tiles", "cand_cap", "nt_store", "tiles_per_block",
+                                 "dense_hits"}
         if unknown:
             raise TypeError("unknown tuning fields: %s" % sorted(unknown))
         tuning = Tuning(fields.get("rows", 0), fields.get("group_tiles", 0),
                         fields.get("cand_cap", 0), fields.get("nt_store", -1),
-                        fields.get("tiles_per_block", 0))
+                        fields.get("tiles_per_block", 0), fields.get("dense_hits", 0))
     return check(lib().ht_set_tuning(ctypes.byref(g), ctypes.byref(tuning)))
 
 

@@ -164,6 +164,7 @@ Tiling choose_tiling(const ht_grid& g)
   // that large batches and very large events use, so that tests reach it on small grids
   t.packed_lists = env_int("HT_PACKED_LISTS", 0) != 0 ? 1 : 0;
   ht_tuning tu;
+  std::memset(&tu, 0, sizeof(tu));
   bool have = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -182,6 +183,29 @@ Tiling choose_tiling(const ht_grid& g)
     t.tiles_per_slab = (g.n_a + t.rows - 1) / t.rows;
     t.n_tiles = g.n_theta * g.n_phi * t.tiles_per_slab;
   }
+  // Stencil peak search of crowded events: a workgroup holds W columns of every slab (four
+  // cells per thread, W a multiple of 8, at most 1024 threads: the widest such W, since each
+  // slab row is read in pieces of W cells, and pieces under 128 bytes fetch cache lines partly
+  // and twice, and row-buffer misses dominate: 32 cells at least, so at most 128 slabs) and
+  // walks dense_rows A rows. It needs LDS tiles for the fill and rows of a multiple of 8 cells
+  // (the peak mask is written a byte per eight cells).
+  const int n_slabs = g.n_theta * g.n_phi;
+  int w = ((4096 / n_slabs) / 8) * 8;
+  const int forced_w = env_int("HT_DENSE_W", 0);
+  if (forced_w >= 8 && forced_w % 8 == 0 && (int64_t)forced_w * n_slabs <= 4096) w = forced_w;
+  w = std::min(w, ((g.n_b + 7) / 8) * 8);
+  const int w_min = forced_w > 0 ? 8 : std::min(32, ((g.n_b + 7) / 8) * 8);
+  t.dense_w = (t.lds_fill && g.n_b % 8 == 0 && w >= w_min) ? w : 0;
+  t.dense_rows = std::max(1, std::min(env_int("HT_DENSE_ROWS", 64), 4096));
+  // default: events with at least 5/16 n_slabs n_b hits, about 0.3 hits per (theta, phi, B)
+  // cell, where the stencil's one pass over the matrix measured faster than the candidate pool
+  // (on the 4x16x1024x1024 grid: 20480 hits; the pool won up to 18k hits, the stencil from 22k);
+  // -1 never
+  int64_t dh = ((int64_t)n_slabs * g.n_b * 5 + 15) / 16;
+  const int forced_dh = env_int("HT_DENSE_HITS", 0);
+  if (forced_dh != 0) dh = forced_dh;
+  if (have && tu.dense_hits != 0) dh = tu.dense_hits;
+  t.dense_hits = (t.dense_w > 0 && dh > 0) ? (int32_t)std::min<int64_t>(dh, 1 << 28) : 0;
   return t;
 }
 
@@ -202,6 +226,7 @@ int check_tuning(const ht_grid& g, const ht_tuning& tu)
   if (tu.nt_store < -1 || tu.nt_store > 2) return fail(HT_EINVAL, "tuning.nt_store must be -1, 0, 1 or 2");
   if (tu.tiles_per_block < 0 || (tu.tiles_per_block > 0 && (!pow2(tu.tiles_per_block) || tu.tiles_per_block > 64)))
     return fail(HT_EINVAL, "tuning.tiles_per_block must be a power of two <= 64");
+  if (tu.dense_hits < -1) return fail(HT_EINVAL, "tuning.dense_hits must be -1, 0 or a hit count");
   return HT_OK;
 }
 
@@ -273,6 +298,9 @@ DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
   // candidate test: enough workgroups to spread a few thousand candidates over the whole chip
   // in one pass (two candidates per wave), few enough that a near-empty event exits at once
   d.test_blocks = std::max(16, std::min(1024, (tl.n_tiles + 15) / 16));
+  d.dense_w = tl.dense_w;
+  d.dense_rows = tl.dense_rows;
+  d.dense_hits = tl.dense_hits;
   d.a2 = t.a2;
   d.phi_cs = t.phi;
   d.th_cs = t.th;
@@ -283,6 +311,11 @@ DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl)
 // Per-event scratch
 // ---------------------------------------------------------------------------------------------
 static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool dense_peaks(const DevGrid& g, int64_t n)
+{
+  return g.dense_w > 0 && g.dense_hits > 0 && n >= g.dense_hits;
+}
 
 bool direct_lists(const DevGrid& g, int64_t n)
 {
@@ -306,7 +339,12 @@ size_t pool_entries(const DevGrid& g, int64_t n)
   return std::min<size_t>(std::max(by_tiles, std::min(cells, bound / 4)), 0xfffffff0u);
 }
 
-size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct)
+static size_t mask_bytes(const DevGrid& g)
+{
+  return ((size_t)g.n_slabs * (size_t)g.n_a * (size_t)g.n_b + 7) / 8;
+}
+
+size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct, int peaks)
 {
   const size_t nn = (size_t)std::max<int64_t>(n, 0);
   size_t b = 0;
@@ -321,15 +359,17 @@ size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct)
   }
   b += al(4 * (size_t)g.n_tiles);             // tile_cnt
   b += al(4 * (size_t)g.n_tiles);             // tile_off
-  b += al(8 * pool_entries(g, n));              // pool
-  b += al(pool_entries(g, n));                  // pk_flag
+  const size_t pe = (peaks & kPeakPool) ? pool_entries(g, n) : 0;
+  b += al(8 * pe);                            // pool
+  b += al(pe);                                // pk_flag
+  if (peaks & kPeakMask) b += al(mask_bytes(g));  // pk_mask
   b += al(4 * (size_t)g.n_tiles);               // ovf_list
   b += al(4 * (size_t)g.n_tiles);             // tile_pk
   b += al(4 * (size_t)n_groups(g));           // group_pk
   return b;
 }
 
-void carve_event_scratch(const DevGrid& g, int64_t n, bool direct, char* p, EvDesc* ev)
+void carve_event_scratch(const DevGrid& g, int64_t n, bool direct, char* p, EvDesc* ev, int peaks)
 {
   const size_t nn = (size_t)std::max<int64_t>(n, 0);
   auto take = [&p](size_t bytes) {
@@ -353,9 +393,10 @@ void carve_event_scratch(const DevGrid& g, int64_t n, bool direct, char* p, EvDe
   }
   ev->tile_cnt = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->tile_off = (uint32_t*)take(4 * (size_t)g.n_tiles);
-  ev->pool_cap = (uint32_t)pool_entries(g, n);
+  ev->pool_cap = (peaks & kPeakPool) ? (uint32_t)pool_entries(g, n) : 0u;
   ev->pool = (uint2*)take(8 * (size_t)ev->pool_cap);
   ev->pk_flag = (uint8_t*)take((size_t)ev->pool_cap);
+  ev->pk_mask = (peaks & kPeakMask) ? (uint8_t*)take(mask_bytes(g)) : nullptr;
   ev->ovf_list = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->tile_pk = (uint32_t*)take(4 * (size_t)g.n_tiles);
   ev->group_pk = (uint32_t*)take(4 * (size_t)n_groups(g));
@@ -557,7 +598,7 @@ int injected_failure(const char* stage)
 }
 
 int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, bool direct,
-                 hipStream_t s, bool* prep_enqueued)
+                 bool any_pool, bool any_dense, hipStream_t s, bool* prep_enqueued)
 {
   EvDesc none;
   std::memset(&none, 0, sizeof(none));
@@ -585,7 +626,10 @@ int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hit
   }
   if ((rc = injected_failure("peaks"))) return rc;
   StageTimer t("peaks", s);
-  return check_launch(launch_peaks(g, none, d_ev, n_ev, s), "peak launch");
+  if (any_pool && (rc = check_launch(launch_peaks(g, none, d_ev, n_ev, s), "peak launch"))) return rc;
+  if (any_dense && (rc = check_launch(launch_peaks_dense(g, none, d_ev, n_ev, s), "stencil peak launch")))
+    return rc;
+  return HT_OK;
 }
 
 // Outputs (peak list, count) may live in device memory or in pinned host memory that is
@@ -625,11 +669,12 @@ int check_accessible(const void* ptr, const char* what)
 bool plan_batch(const DevGrid& g, const ht_event* events, int n_events, std::vector<size_t>* offs,
                 size_t* total, int64_t* max_hits)
 {
+  auto layout = [&g](int64_t n) { return dense_peaks(g, n) ? kPeakMask : kPeakPool; };
   bool direct = g.lds_fill != 0;
   size_t direct_bytes = 0;
   for (int i = 0; i < n_events; ++i) {
     direct = direct && direct_lists(g, events[i].n_hits);
-    direct_bytes += event_scratch_bytes(g, events[i].n_hits, true);
+    direct_bytes += event_scratch_bytes(g, events[i].n_hits, true, layout(events[i].n_hits));
   }
   if (direct_bytes > kBatchDirectMax) direct = false;
   offs->assign((size_t)n_events, 0);
@@ -638,7 +683,7 @@ bool plan_batch(const DevGrid& g, const ht_event* events, int n_events, std::vec
   for (int i = 0; i < n_events; ++i) {
     *max_hits = std::max(*max_hits, events[i].n_hits);
     (*offs)[i] = *total;
-    *total += event_scratch_bytes(g, events[i].n_hits, direct);
+    *total += event_scratch_bytes(g, events[i].n_hits, direct, layout(events[i].n_hits));
   }
   return direct;
 }
@@ -675,7 +720,11 @@ int enqueue_event(const DevGrid& g, const EvDesc& ev, int64_t nh, bool direct, b
     }
     if ((rc = injected_failure("peaks"))) return rc;
     HT_STAGE(t, "peaks");
-    if ((rc = check_launch(launch_peaks(g, ev, nullptr, 1, s), "peak launch"))) return rc;
+    if (ev.dense) {
+      if ((rc = check_launch(launch_peaks_dense(g, ev, nullptr, 1, s), "stencil peak launch"))) return rc;
+    } else if ((rc = check_launch(launch_peaks(g, ev, nullptr, 1, s), "peak launch"))) {
+      return rc;
+    }
   }
 #undef HT_STAGE
   return HT_OK;
@@ -699,12 +748,16 @@ int run_event(const ht_grid* grid, const float* x, const float* y, const float* 
   const int64_t nh = do_fill ? n : 0;
   const bool atomic = force_atomic || !p.g.lds_fill;
   const bool direct = !atomic && direct_lists(p.g, nh);
+  // crowded events of the fused call: peaks from the stencil over the written matrix
+  const bool dense = do_fill && do_peaks && !atomic && dense_peaks(p.g, nh);
+  const int layout = dense ? kPeakMask : kPeakPool;
   Workspace* w;
-  if ((rc = get_workspace(p.dev, p.s, event_scratch_bytes(p.g, nh, direct), &w))) return rc;
+  if ((rc = get_workspace(p.dev, p.s, event_scratch_bytes(p.g, nh, direct, layout), &w))) return rc;
   if ((rc = ensure_counters(w, 1, p.s))) return rc;
   EvDesc ev;
   std::memset(&ev, 0, sizeof(ev));
-  carve_event_scratch(p.g, nh, direct, w->dev, &ev);
+  carve_event_scratch(p.g, nh, direct, w->dev, &ev, layout);
+  ev.dense = dense ? 1 : 0;
   use_counters(w, 0, &ev);
   ev.x = x;
   ev.y = y;
@@ -805,11 +858,16 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
   if ((rc = ensure_ev_staging(w, n_events, p.s))) return rc;
   if ((rc = ensure_counters(w, n_events, p.s))) return rc;
   const uint64_t cells = n_cells(*grid);
+  bool any_pool = false, any_dense = false;
   for (int32_t i = 0; i < n_events; ++i) {
     const ht_event& ev = events[i];
     EvDesc& d = w->h_ev[i];
     std::memset(&d, 0, sizeof(d));
-    carve_event_scratch(p.g, ev.n_hits, direct, w->dev + offs[i], &d);
+    const bool dense = p.g.lds_fill && dense_peaks(p.g, ev.n_hits);
+    any_pool = any_pool || !dense;
+    any_dense = any_dense || dense;
+    carve_event_scratch(p.g, ev.n_hits, direct, w->dev + offs[i], &d, dense ? kPeakMask : kPeakPool);
+    d.dense = dense ? 1 : 0;
     use_counters(w, i, &d);
     d.x = x ? x + ev.hit_offset : nullptr;
     d.y = y ? y + ev.hit_offset : nullptr;
@@ -834,7 +892,7 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(descriptors)");
     if ((e = hipEventRecord(w->ev_copied, p.s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
     bool prep_enqueued = false;
-    rc = launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, p.s, &prep_enqueued);
+    rc = launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, any_pool, any_dense, p.s, &prep_enqueued);
     if (prep_enqueued) flip_counters(w, n_events);
     return rc;
   }
@@ -844,7 +902,7 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
     unsigned char* q = key.data();
     std::memcpy(q, &p.g, sizeof(DevGrid));
     q += sizeof(DevGrid);
-    const int64_t ints[4] = {n_events, max_hits_b, p.dev, direct ? 1 : 0};
+    const int64_t ints[4] = {n_events, max_hits_b, p.dev, (direct ? 1 : 0) | (any_pool ? 2 : 0) | (any_dense ? 4 : 0)};
     std::memcpy(q, ints, sizeof(ints));
     q += sizeof(ints);
     const void* ptrs[2] = {w->d_ev, w->h_ev};
@@ -864,7 +922,8 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
     e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, w->capture);
     bool captured_prep = false;
     int lrc = e == hipSuccess
-                  ? launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, w->capture, &captured_prep)
+                  ? launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, any_pool, any_dense, w->capture,
+                                 &captured_prep)
                   : HT_EDEVICE;
     t_capturing = false;
     hipGraph_t graph = nullptr;
@@ -918,6 +977,7 @@ int ht_get_tuning(const ht_grid* grid, ht_tuning* tuning)
   tuning->cand_cap = t.cand_cap;
   tuning->nt_store = t.nt_store;
   tuning->tiles_per_block = t.fill_tiles;
+  tuning->dense_hits = t.dense_w > 0 && t.dense_hits > 0 ? t.dense_hits : -1;
   return HT_OK;
 }
 

@@ -401,7 +401,11 @@ __global__ __launch_bounds__(kBlock) void k_fill(DevGrid g, EvDesc ev0, const Ev
     lds_barrier();
 
     const uint32_t cell0 = ((uint32_t)slab * (uint32_t)g.n_a + (uint32_t)a0) * nb;
-    if (EMIT) {
+    if (EMIT && e.dense) {
+      // crowded event: its peaks come from the stencil over the written matrix, which only
+      // needs the group's peak count cleared
+      if (threadIdx.x == 0 && tile % g.group_tiles == 0) gp(e.group_pk)[tile / g.group_tiles] = 0u;
+    } else if (EMIT) {
       // candidates are pooled before the tile is written, so the wait for the pool reservation
       // never falls behind this tile's stores (the memory counter a wave waits on counts stores
       // too); each pass keeps several 16-byte LDS reads in flight per lane

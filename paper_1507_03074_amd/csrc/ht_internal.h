@@ -52,6 +52,9 @@ struct DevGrid {
   int32_t phi_sectors;     // 1: phi cells are independent sectors (no phi widening or neighbours)
   int32_t packed_lists;    // 1: always the counting-sort (packed) slab lists, never direct ones
   int32_t test_blocks;     // workgroups per event of the candidate test
+  int32_t dense_w;         // B columns per workgroup of the stencil peak search (0: unavailable)
+  int32_t dense_rows;      // A rows per workgroup of the stencil peak search
+  int32_t dense_hits;      // events with at least this many hits take the stencil (0: never)
   const float* a2;         // device [n_a]
   const float* phi_cs;     // device [2 * 2 n_phi] (cos, sin)
   const float* th_cs;      // device [2 * (2 n_theta + 1)] (cos, sin)
@@ -84,6 +87,8 @@ struct EvDesc {
   uint32_t* ovf_list;   // [n_tiles] tiles whose candidates did not fit the pool
   uint32_t* tile_pk;    // [n_tiles] peaks per tile
   uint32_t* group_pk;   // [n_groups] peaks per group of tiles
+  int32_t dense;        // 1: peaks from the stencil over the matrix (crowded events), not the pool
+  uint8_t* pk_mask;     // [cells / 8] peak bits of a dense event, in cell order
 };
 
 // Launch shape of one grid (ht_tuning resolved against the defaults).
@@ -91,6 +96,7 @@ struct Tiling {
   int32_t rows, tiles_per_slab, n_tiles, cand_cap, lds_fill, group_tiles, nt_store, fill_tiles;
   int32_t pool_bound;
   int32_t packed_lists;
+  int32_t dense_w, dense_rows, dense_hits;  // stencil peak search (DevGrid fields of these names)
 };
 Tiling choose_tiling(const ht_grid& g);
 
@@ -112,9 +118,16 @@ DevGrid make_devgrid(const ht_grid& g, const DevTables& t, const Tiling& tl);
 
 // Whether an event of n_hits hits uses direct slab lists (see kDirectListMax).
 bool direct_lists(const DevGrid& g, int64_t n_hits);
+// Whether the fused fill + peaks of an event of n_hits hits searches its peaks with the stencil
+// over the matrix (crowded events) instead of the candidate pool.
+bool dense_peaks(const DevGrid& g, int64_t n_hits);
+// What an event's peak-search scratch holds: the candidate pool, the stencil's peak mask, or
+// both (request-loop slots, which serve events of either kind).
+enum PeakScratch { kPeakPool = 1, kPeakMask = 2 };
 // Bytes of per-event scratch for a grid tiling and an event size, and the carving of it.
-size_t event_scratch_bytes(const DevGrid& g, int64_t n_hits, bool direct);
-void carve_event_scratch(const DevGrid& g, int64_t n_hits, bool direct, char* base, EvDesc* ev);
+size_t event_scratch_bytes(const DevGrid& g, int64_t n_hits, bool direct, int peaks = kPeakPool);
+void carve_event_scratch(const DevGrid& g, int64_t n_hits, bool direct, char* base, EvDesc* ev,
+                         int peaks = kPeakPool);
 
 // Kernel launchers (ht_kernels.hip). `evs` is a device array of n_ev descriptors, or nullptr
 // for a single event passed by value in `ev0`. `max_hits` bounds n_hits over the events.
@@ -126,6 +139,9 @@ hipError_t launch_candidates(const DevGrid& g, const EvDesc& ev0, const EvDesc* 
                              hipStream_t s);
 hipError_t launch_peaks(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                         hipStream_t s);
+// Stencil peak search and ordered write of the events marked dense (others are skipped).
+hipError_t launch_peaks_dense(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                              hipStream_t s);
 // Plain fill: zero the matrix, then one global atomicAdd per vote (reference path and the
 // fallback for B rows too wide for an LDS tile).
 hipError_t launch_fill_atomic(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
@@ -159,7 +175,9 @@ int make_device_grid(const ht_grid& g, int dev, DevGrid* out);
 // descriptors are already in device memory.
 // *prep_enqueued is set once the preparation (which counts into and clears the events' counter
 // arrays) is on the stream.
+// any_pool / any_dense: whether some event searches its peaks through the candidate pool /
+// the stencil (only the kernels needed are launched).
 int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, bool direct,
-                 hipStream_t s, bool* prep_enqueued);
+                 bool any_pool, bool any_dense, hipStream_t s, bool* prep_enqueued);
 
 }  // namespace ht

@@ -493,6 +493,7 @@ __device__ __forceinline__ void count_peak(const DevGrid& g, const EvDesc& e, ui
 __global__ __launch_bounds__(kBlock) void k_peak_test(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   EvDesc e = load_ev(ev0, evs);
+  if (e.dense) return;  // uniform: searched by the stencil
   const int lane = threadIdx.x & 63, half = lane >> 5, k = lane & 31;
   // workgroups are dealt to the 8 XCDs in turn: give each XCD one contiguous run of blocks
   const uint32_t blk =
@@ -571,6 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
   __shared__ uint32_t s_first[kGroupTiles];
   __shared__ uint32_t smem[32];
   EvDesc e = load_ev(ev0, evs);
+  if (e.dense) return;  // uniform: written by k_peak_write_dense
   const int G = blockIdx.x;
   const int t0 = G * g.group_tiles;
   const bool a8 = ((uintptr_t)e.out & 7u) == 0;
@@ -675,6 +677,289 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
       const int64_t o = base + s_out[tl] + r + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
       if (pk && o < e.cap) st_peak(e.out, o, c, v, a8);
       r += (uint32_t)__popcll(m);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Peak search of crowded events: an LDS-halo stencil over the whole matrix (one read of it), in
+// place of the candidate pool. A workgroup owns one chunk of W B columns of every (theta, phi)
+// slab and walks down a segment of S A rows; thread (slab, q) holds four consecutive cells of
+// its slab's chunk. The strict maximum under (votes, -index) splits the 80 neighbours of a cell
+// c into those of lower index ("before": slabs of lower index, the row above in its own slab,
+// the cell left of it) and the others ("after"). A before-neighbour w beats c iff w >= v(c),
+// i.e. w + 1 > v(c); an after-neighbour iff w > v(c). So with M(c) the maximum over the after-
+// neighbours of w and over the before-neighbours of w + 1 (absent cells count 0),
+//   c is a peak  iff  v(c) >= T  and  v(c) >= M(c).
+// Per row a the workgroup forms R3(a, b) = the maximum over b-1..b+1 in registers, then
+// W9(a-1, b) = the maximum of R3 over rows a-2..a (the 3 x 3 (A, B) window) into LDS, twice:
+// plain and plus one. The test of row a-1 takes from LDS, for each of the eight neighbour slabs,
+// the plain or the plus-one window maximum, whichever its order relative to the thread's slab
+// asks for (fixed per thread: the addresses are computed once), and its own slab's parts from
+// registers. Cells outside theta, A or B count as zero (or one where a plus one is added, which
+// never decides a test: a tested cell holds at least T >= 1 votes); phi wraps (no phi
+// neighbours with phi sectors). Each row's loads are issued kDenseAhead rows ahead, and the two LDS buffers
+// alternate, so each row needs one barrier. Peaks go to a bit mask of the matrix in cell order
+// (one byte per eight cells, written by one lane), their count per group of tiles to group_pk.
+// ---------------------------------------------------------------------------------------------
+constexpr int kDenseAhead = 4;
+
+__device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) { return max(a, max(b, c)); }
+
+__global__ __launch_bounds__(1024) void k_peak_dense(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  // two buffers, each [plain W9 of every slab | W9 + 1 of every slab | W zeros]
+  extern __shared__ uint32_t s_lds[];
+  EvDesc e = load_ev(ev0, evs);
+  if (!e.dense) return;  // uniform: this event's peaks come from the candidate pool
+  const int W = g.dense_w, S = g.dense_rows, np = g.n_phi, nsl = g.n_slabs;
+  const uint32_t nb = (uint32_t)g.n_b;
+  const uint32_t plus_ofs = (uint32_t)nsl * (uint32_t)W;
+  const uint32_t zero_ofs = 2u * plus_ofs;
+  const uint32_t buf_words = zero_ofs + (uint32_t)W;
+  for (int i = threadIdx.x; i < W; i += blockDim.x) {
+    s_lds[zero_ofs + i] = 0u;
+    s_lds[buf_words + zero_ofs + i] = 0u;
+  }
+  const int n_chunks = (g.n_b + W - 1) / W;
+  // Workgroups are dealt to the eight XCDs in turn; renumbered so that each XCD takes one
+  // contiguous range (adjacent chunks of the same rows, then the next rows), the cache lines that
+  // neighbouring workgroups share (chunk edges, segment edges) are fetched into one L2. The row
+  // bounds are uniform (read from the first lane), so the row loop and its tests stay scalar.
+  const uint32_t G = gridDim.x;
+  const uint32_t lb = G % 8u ? blockIdx.x : (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u;
+  const int chunk = __builtin_amdgcn_readfirstlane((int)lb % n_chunks);
+  const int a_beg = __builtin_amdgcn_readfirstlane(((int)lb / n_chunks) * S);
+  const int a_end = min(a_beg + S, g.n_a);
+  const int qpr = W / 4;  // quads per slab in a chunk (even: W is a multiple of 8)
+  const int s_raw = (int)threadIdx.x / qpr;
+  const int qi = (int)threadIdx.x - s_raw * qpr;
+  const bool live = s_raw < nsl;
+  const int s = live ? s_raw : 0;
+  const int b0 = chunk * W + 4 * qi;
+  const bool in_row = live && b0 < g.n_b;
+  const int t = s / np, p = s - t * np;
+  // word offsets (within a buffer) of what each of the eight neighbour slabs contributes: the
+  // plain window maximum (after), the plus-one one (before) or zeros (absent)
+  uint32_t nofs[8];
+  {
+    int k = 0;
+#pragma unroll
+    for (int dt = -1; dt <= 1; ++dt)
+#pragma unroll
+      for (int dp = -1; dp <= 1; ++dp) {
+        if (dt == 0 && dp == 0) continue;
+        const int tt = t + dt;
+        const int pp = dp < 0 ? (p == 0 ? np - 1 : p - 1) : (dp > 0 ? (p + 1 == np ? 0 : p + 1) : p);
+        const bool ok = tt >= 0 && tt < g.n_theta && !(g.phi_sectors && dp != 0);
+        const int sn = tt * np + pp;
+        nofs[k++] = ok ? (sn < s ? plus_ofs : 0u) + (uint32_t)sn * (uint32_t)W + 4u * (uint32_t)qi
+                       : zero_ofs + 4u * (uint32_t)qi;
+      }
+  }
+  const uint32_t my_ofs = (uint32_t)s * (uint32_t)W + 4u * (uint32_t)qi;
+  const uint32_t T = g.threshold;
+  // per-lane pointers into row 0 of the slab: the quad (clamped into the row for lanes past a
+  // ragged row end, whose values are never used) and its left and right neighbours (clamped
+  // into the row; masked to zero at the row ends)
+  const int bc = min(b0, g.n_b - 4);
+  const GLOBAL uint32_t* q0 = gp((const uint32_t*)e.acc) + (size_t)s * (size_t)g.n_a * nb + bc;
+  const GLOBAL uint32_t* l0 = q0 + (bc > 0 ? -1 : 0);
+  const GLOBAL uint32_t* h0 = q0 + (bc + 4 < g.n_b ? 4 : 3);
+  const uint32_t lmask = b0 > 0 ? 0xffffffffu : 0u;
+  const uint32_t hmask = b0 + 4 < g.n_b ? 0xffffffffu : 0u;
+  uint8_t* mask = e.pk_mask;
+  const uint32_t rows_log2 = (uint32_t)__ffs(g.rows) - 1u;
+  const uint32_t gt_log2 = (uint32_t)__ffs(g.group_tiles) - 1u;
+  const uint32_t row_cells0 = (uint32_t)s * (uint32_t)g.n_a * nb + (uint32_t)b0;
+  const bool writer = (qi & 1) == 0 && in_row;
+  const uint32_t tile0 = (uint32_t)s * (uint32_t)g.tiles_per_slab;
+  // R3 of rows a-2 and a-1, the cells of row a-1 and the cells left and right of them
+  uint32_t rm2[4] = {0u, 0u, 0u, 0u}, rm1[4] = {0u, 0u, 0u, 0u}, vm1[4] = {0u, 0u, 0u, 0u};
+  uint32_t lm1 = 0u, hm1 = 0u;
+  uint32_t buf = 0u;
+
+  // row a (uniform) of the thread's quad and its two neighbours
+#define HT_DENSE_LOAD(a_, v_, l_, h_)                                                          \
+  do {                                                                                         \
+    const size_t ro_ = (size_t)(a_) * nb;                                                      \
+    const u32x4 w_ = *reinterpret_cast<const GLOBAL u32x4*>(q0 + ro_);                         \
+    (v_)[0] = w_.x;                                                                            \
+    (v_)[1] = w_.y;                                                                            \
+    (v_)[2] = w_.z;                                                                            \
+    (v_)[3] = w_.w;                                                                            \
+    (l_) = l0[ro_] & lmask;                                                                    \
+    (h_) = h0[ro_] & hmask;                                                                    \
+  } while (0)
+  // Row a_ (cells v_, left l_, right h_; zeros outside the matrix) arrives: its R3 completes W9
+  // of row a_ - 1, which is tested when test_ (uniform); the peak bits of that row go to the
+  // mask, one byte per eight cells (the odd lane's four bits join the even lane's: same slab,
+  // next quad), and their count to the row's group of tiles (rows and group_tiles are powers
+  // of two).
+#define HT_DENSE_STEP(a_, v_, l_, h_, test_)                                                   \
+  do {                                                                                         \
+    uint32_t r_[4];                                                                            \
+    r_[0] = max3u((l_), (v_)[0], (v_)[1]);                                                     \
+    r_[1] = max3u((v_)[0], (v_)[1], (v_)[2]);                                                  \
+    r_[2] = max3u((v_)[1], (v_)[2], (v_)[3]);                                                  \
+    r_[3] = max3u((v_)[2], (v_)[3], (h_));                                                     \
+    if (test_) {                                                                               \
+      uint32_t* B_ = s_lds + buf * buf_words;                                                  \
+      const u32x4 w9_ = {max3u(rm2[0], rm1[0], r_[0]), max3u(rm2[1], rm1[1], r_[1]),           \
+                         max3u(rm2[2], rm1[2], r_[2]), max3u(rm2[3], rm1[3], r_[3])};          \
+      const u32x4 w9p_ = {w9_.x + 1u, w9_.y + 1u, w9_.z + 1u, w9_.w + 1u};                     \
+      if (live) {                                                                              \
+        *reinterpret_cast<u32x4*>(B_ + my_ofs) = w9_;                                          \
+        *reinterpret_cast<u32x4*>(B_ + plus_ofs + my_ofs) = w9p_;                              \
+      }                                                                                        \
+      lds_barrier();                                                                           \
+      uint32_t m_[4];                                                                          \
+      m_[0] = max3u(max(rm2[0], lm1) + 1u, r_[0], max(vm1[1], T));                             \
+      m_[1] = max3u(max(rm2[1], vm1[0]) + 1u, r_[1], max(vm1[2], T));                          \
+      m_[2] = max3u(max(rm2[2], vm1[1]) + 1u, r_[2], max(vm1[3], T));                          \
+      m_[3] = max3u(max(rm2[3], vm1[2]) + 1u, r_[3], max(hm1, T));                             \
+      u32x4 nw_[8];                                                                            \
+      _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_)                                         \
+        nw_[k_] = *reinterpret_cast<const u32x4*>(B_ + nofs[k_]);                              \
+      m_[0] = max3u(m_[0], max3u(nw_[0].x, nw_[1].x, nw_[2].x),                                \
+                    max3u(nw_[3].x, nw_[4].x, max3u(nw_[5].x, nw_[6].x, nw_[7].x)));           \
+      m_[1] = max3u(m_[1], max3u(nw_[0].y, nw_[1].y, nw_[2].y),                                \
+                    max3u(nw_[3].y, nw_[4].y, max3u(nw_[5].y, nw_[6].y, nw_[7].y)));           \
+      m_[2] = max3u(m_[2], max3u(nw_[0].z, nw_[1].z, nw_[2].z),                                \
+                    max3u(nw_[3].z, nw_[4].z, max3u(nw_[5].z, nw_[6].z, nw_[7].z)));           \
+      m_[3] = max3u(m_[3], max3u(nw_[0].w, nw_[1].w, nw_[2].w),                                \
+                    max3u(nw_[3].w, nw_[4].w, max3u(nw_[5].w, nw_[6].w, nw_[7].w)));           \
+      uint32_t nib_ = 0u;                                                                      \
+      _Pragma("unroll") for (int i_ = 0; i_ < 4; ++i_)                                         \
+        nib_ |= vm1[i_] >= m_[i_] ? (1u << i_) : 0u;                                           \
+      nib_ = in_row ? nib_ : 0u;                                                               \
+      buf ^= 1u;                                                                               \
+      const uint32_t hi_ = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)nib_, 0x101, 0xf, 0xf, false); \
+      if (writer) {                                                                            \
+        const uint32_t byte_ = (nib_ | (hi_ << 4)) & 0xffu;                                    \
+        gp(mask)[(row_cells0 + (uint32_t)((a_) - 1) * nb) >> 3] = (uint8_t)byte_;              \
+        if (byte_)                                                                             \
+          gatomic_add(e.group_pk + ((tile0 + ((uint32_t)((a_) - 1) >> rows_log2)) >> gt_log2), \
+                      (uint32_t)__popc(byte_));                                                \
+      }                                                                                        \
+    }                                                                                          \
+    _Pragma("unroll") for (int i_ = 0; i_ < 4; ++i_) {                                         \
+      rm2[i_] = rm1[i_];                                                                       \
+      rm1[i_] = r_[i_];                                                                        \
+      vm1[i_] = (v_)[i_];                                                                      \
+    }                                                                                          \
+    lm1 = (l_);                                                                                \
+    hm1 = (h_);                                                                                \
+  } while (0)
+
+  const uint32_t zq[4] = {0u, 0u, 0u, 0u};
+  // row a_beg - 1 (zeros above the matrix), never tested
+  if (a_beg > 0) {
+    uint32_t v[4], l, h;
+    HT_DENSE_LOAD(a_beg - 1, v, l, h);
+    HT_DENSE_STEP(a_beg - 1, v, l, h, false);
+  } else {
+    HT_DENSE_STEP(a_beg - 1, zq, 0u, 0u, false);
+  }
+  // rows a_beg .. last, all inside the matrix, loaded kDenseAhead at a time; row a tests a - 1
+  const int last = min(a_end, g.n_a - 1);
+  int a = a_beg;
+  for (; a + kDenseAhead - 1 <= last; a += kDenseAhead) {  // uniform
+    uint32_t v[kDenseAhead][4], l[kDenseAhead], h[kDenseAhead];
+#pragma unroll
+    for (int u = 0; u < kDenseAhead; ++u) HT_DENSE_LOAD(a + u, v[u], l[u], h[u]);
+#pragma unroll
+    for (int u = 0; u < kDenseAhead; ++u) HT_DENSE_STEP(a + u, v[u], l[u], h[u], a + u > a_beg);
+  }
+  for (; a <= last; ++a) {  // uniform
+    uint32_t v[4], l, h;
+    HT_DENSE_LOAD(a, v, l, h);
+    HT_DENSE_STEP(a, v, l, h, a > a_beg);
+  }
+  // below the matrix: row n_a is zeros, and tests row n_a - 1
+  if (a_end == g.n_a) HT_DENSE_STEP(g.n_a, zq, 0u, 0u, true);
+#undef HT_DENSE_STEP
+#undef HT_DENSE_LOAD
+}
+
+// Ordered output of a dense event: one workgroup per group of tiles (a contiguous range of
+// cells); its output offset is the sum of the earlier groups' peak counts. Thread t takes the
+// t-th of 256 equal, contiguous pieces of the group's part of the mask, all loaded at once; one
+// block scan of the pieces' peak counts gives each thread where its peaks go, in cell order.
+__global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  __shared__ uint32_t smem[32];
+  EvDesc e = load_ev(ev0, evs);
+  if (!e.dense) return;
+  const int G = blockIdx.x;
+  const int t0 = G * g.group_tiles;
+  const int nt = min(g.group_tiles, g.n_tiles - t0);
+  const bool a8 = ((uintptr_t)e.out & 7u) == 0;
+  uint32_t part = 0;
+  for (int i0 = 0; i0 < G; i0 += 4 * kBlock) {  // uniform
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * kBlock + (int)threadIdx.x;
+      w[k] = i < G ? gp(e.group_pk)[i] : 0u;
+    }
+    part += w[0] + w[1] + w[2] + w[3];
+  }
+  const int64_t base = (int64_t)block_sum(part, smem);
+  if (G == (int)gridDim.x - 1 && threadIdx.x == 0) *gp(e.n_found) = base + gp(e.group_pk)[G];
+  if (base >= e.cap) return;  // uniform
+  uint32_t c_beg, L0, c_last, L1;
+  tile_range(g, t0, &c_beg, &L0);
+  tile_range(g, t0 + nt - 1, &c_last, &L1);
+  // the group's cells are [c_beg, c_last + L1), every bound a multiple of 8 (n_b is); the
+  // thread's piece is bytes [b_lo, b_hi) of the mask, in whole 32-bit words when aligned
+  const uint64_t by0 = c_beg >> 3, by1 = ((uint64_t)c_last + L1) >> 3;
+  const uint64_t per = (((by1 - by0) + kBlock - 1) / kBlock + 3) & ~(uint64_t)3;  // multiple of 4
+  const uint64_t b_lo = min(by1, by0 + per * threadIdx.x), b_hi = min(by1, b_lo + per);
+  const GLOBAL uint8_t* mask = gp((const uint8_t*)e.pk_mask);
+  const bool words = (by0 & 3u) == 0 && (by1 & 3u) == 0;  // uniform
+  constexpr int kMaxWords = 16;  // up to 64 bytes (512 cells) per thread held in registers
+  uint32_t wv[kMaxWords];
+  uint32_t cnt = 0;
+  const int nw = (int)((b_hi - b_lo + 3) / 4);
+  if (words && per <= 4 * kMaxWords) {  // uniform
+    const GLOBAL uint32_t* m32 = reinterpret_cast<const GLOBAL uint32_t*>(mask + b_lo);
+#pragma unroll
+    for (int k = 0; k < kMaxWords; ++k) wv[k] = k < nw ? m32[k] : 0u;
+#pragma unroll
+    for (int k = 0; k < kMaxWords; ++k) cnt += (uint32_t)__popc(wv[k]);
+  } else {
+    for (uint64_t b = b_lo; b < b_hi; ++b) cnt += (uint32_t)__popc(mask[b]);
+  }
+  uint32_t tot;
+  int64_t o = base + block_excl_scan(cnt, smem, &tot);
+  if (o >= e.cap || cnt == 0) return;
+  if (words && per <= 4 * kMaxWords) {  // uniform
+#pragma unroll
+    for (int k = 0; k < kMaxWords; ++k) {
+      uint32_t bits = wv[k];
+      while (bits) {
+        const int i = __ffs(bits) - 1;
+        bits &= bits - 1u;
+        if (o < e.cap) {
+          const uint32_t c = (uint32_t)((b_lo + 4u * (uint32_t)k) * 8u) + (uint32_t)i;
+          st_peak(e.out, o, c, gp(e.acc)[c], a8);
+        }
+        ++o;
+      }
+    }
+  } else {
+    for (uint64_t b = b_lo; b < b_hi; ++b) {
+      uint32_t bits = mask[b];
+      while (bits) {
+        const int i = __ffs(bits) - 1;
+        bits &= bits - 1u;
+        if (o < e.cap) {
+          const uint32_t c = (uint32_t)(b * 8u) + (uint32_t)i;
+          st_peak(e.out, o, c, gp(e.acc)[c], a8);
+        }
+        ++o;
+      }
     }
   }
 }
@@ -852,6 +1137,22 @@ hipError_t launch_peaks(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, 
 {
   hipLaunchKernelGGL(k_peak_test, dim3(g.test_blocks, n_ev), dim3(kBlock), 0, s, g, ev0, evs);
   hipLaunchKernelGGL(k_peak_write, dim3(n_groups(g), n_ev), dim3(kBlock), 0, s, g, ev0, evs);
+  return hipGetLastError();
+}
+
+int dense_blocks(const DevGrid& g)
+{
+  return ((g.n_b + g.dense_w - 1) / g.dense_w) * ((g.n_a + g.dense_rows - 1) / g.dense_rows);
+}
+
+hipError_t launch_peaks_dense(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
+                              hipStream_t s)
+{
+  const int threads = ((g.n_slabs * (g.dense_w / 4) + 63) / 64) * 64;
+  // two buffers of plain and plus-one window maxima of every slab, and a zero row each
+  const size_t lds = 2 * ((size_t)2 * g.n_slabs * g.dense_w + g.dense_w) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_peak_dense, dim3(dense_blocks(g), n_ev), dim3(threads), lds, s, g, ev0, evs);
+  hipLaunchKernelGGL(k_peak_write_dense, dim3(n_groups(g), n_ev), dim3(kBlock), 0, s, g, ev0, evs);
   return hipGetLastError();
 }
 

@@ -85,9 +85,11 @@ extern "C" int ht_fill_peaks_noalloc(const ht_grid* grid, const float* x, const 
   const Tiling tl = choose_tiling(*grid);
   DevGrid g = make_devgrid(*grid, DevTables(), tl);
   const bool atomic = !g.lds_fill;
+  const bool dense = !atomic && dense_peaks(g, n_hits);
+  const int layout = dense ? kPeakMask : kPeakPool;
   const size_t room = kNoAllocBytes - kEvOff;
-  bool direct = !atomic && direct_lists(g, n_hits) && event_scratch_bytes(g, n_hits, true) <= room;
-  const size_t need = event_scratch_bytes(g, n_hits, direct);
+  bool direct = !atomic && direct_lists(g, n_hits) && event_scratch_bytes(g, n_hits, true, layout) <= room;
+  const size_t need = event_scratch_bytes(g, n_hits, direct, layout);
   if (need > room)
     return fail(HT_EINVAL,
                 "ht_fill_peaks_noalloc: this event needs %zu bytes of scratch; the fixed scratch "
@@ -129,7 +131,8 @@ extern "C" int ht_fill_peaks_noalloc(const ht_grid* grid, const float* x, const 
 
   EvDesc ev;
   std::memset(&ev, 0, sizeof(ev));
-  carve_event_scratch(g, n_hits, direct, base + kEvOff, &ev);
+  carve_event_scratch(g, n_hits, direct, base + kEvOff, &ev, layout);
+  ev.dense = dense ? 1 : 0;
   uint32_t* pair = (uint32_t*)base;
   ev.slab_cnt = pair + (g_parity[dev] ? kCounterWords : 0);
   ev.slab_cnt_next = pair + (g_parity[dev] ? 0 : kCounterWords);

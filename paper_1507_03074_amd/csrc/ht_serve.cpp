@@ -73,6 +73,7 @@ struct ht_server {
   uint64_t cells = 0;
   size_t scratch_bytes = 0;
   bool direct = false;
+  int layout = kPeakPool;       // slots hold a candidate pool, and a peak mask when events can be crowded
   char* arena = nullptr;        // device: all slots
   uint32_t* ctr = nullptr;      // device: slab counters of all slots
   char* host_out = nullptr;     // pinned: per-slot peak lists and counts
@@ -123,6 +124,7 @@ int launch(ht_server* sv, Batch& b)
   hipStream_t s = sv->streams[b.stream];
   const int64_t mh = sv->opts.max_hits;
   int64_t max_n = 0;
+  bool any_pool = false, any_dense = false;
   hipError_t e;
   for (size_t i = 0; i < b.reqs.size(); ++i) {
     Request* r = b.reqs[i];
@@ -133,7 +135,11 @@ int launch(ht_server* sv, Batch& b)
       return fail_hip(e, "hipMemcpyAsync(hits)");
     EvDesc& d = sv->h_ev[b.stream][i];
     std::memset(&d, 0, sizeof(d));
-    carve_event_scratch(sv->g, mh, sv->direct, sl.scratch, &d);
+    carve_event_scratch(sv->g, mh, sv->direct, sl.scratch, &d, sv->layout);
+    // crowded events search their peaks with the stencil (the slot holds both layouts)
+    d.dense = (sv->layout & kPeakMask) && dense_peaks(sv->g, r->n) ? 1 : 0;
+    any_pool = any_pool || !d.dense;
+    any_dense = any_dense || d.dense;
     d.slab_cnt = sl.ctr + (sl.parity ? kCounterWords : 0);
     d.slab_cnt_next = sl.ctr + (sl.parity ? 0 : kCounterWords);
     d.x = sl.hits;
@@ -150,8 +156,8 @@ int launch(ht_server* sv, Batch& b)
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail_hip(e, "hipMemcpyAsync(descriptors)");
   bool prep_enqueued = false;
-  int rc = launch_batch(sv->g, sv->d_ev[b.stream], (int)b.reqs.size(), max_n, sv->direct, s,
-                        &prep_enqueued);
+  int rc = launch_batch(sv->g, sv->d_ev[b.stream], (int)b.reqs.size(), max_n, sv->direct, any_pool,
+                        any_dense, s, &prep_enqueued);
   // a slot switches counter arrays only once the preparation that counts into this one and
   // clears the other is on the stream
   if (prep_enqueued)
@@ -262,7 +268,8 @@ int ht_serve_create(const ht_grid* grid, const ht_serve_opts* opts, ht_server** 
   }
   sv->cells = n_cells(*grid);
   sv->direct = direct_lists(sv->g, opts->max_hits);
-  sv->scratch_bytes = event_scratch_bytes(sv->g, opts->max_hits, sv->direct);
+  sv->layout = kPeakPool | (dense_peaks(sv->g, opts->max_hits) ? kPeakMask : 0);
+  sv->scratch_bytes = event_scratch_bytes(sv->g, opts->max_hits, sv->direct, sv->layout);
   const size_t slot_bytes = al(4 * sv->cells) + al(sv->scratch_bytes) + al(12 * (size_t)opts->max_hits);
   const int64_t n_slots = std::min<int64_t>(opts->hbm_budget_bytes / (int64_t)slot_bytes, 4096);
   if (n_slots < 1) {

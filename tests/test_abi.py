@@ -126,16 +126,19 @@ def test_tuning_validated_and_applied_on_host(lib):
     assert default["rows"] == B.ht_tiling(spec)["rows"]
     for bad in [dict(rows=3), dict(rows=128), dict(rows=32),  # 32 x 1024 x 4 B exceeds the LDS tile
                 dict(group_tiles=8), dict(cand_cap=3), dict(cand_cap=8192), dict(nt_store=3),
-                dict(tiles_per_block=3), dict(tiles_per_block=128), dict(tiles_per_block=-1)]:
+                dict(tiles_per_block=3), dict(tiles_per_block=128), dict(tiles_per_block=-1),
+                dict(dense_hits=-2)]:
         with pytest.raises(B.HTError):
             B.ht_set_tuning(spec, **bad)
         assert B.ht_get_tuning(spec).as_dict() == default
     assert default["tiles_per_block"] >= 1 and default["nt_store"] in (0, 1, 2)
-    B.ht_set_tuning(spec, rows=4, group_tiles=32, cand_cap=128, nt_store=2, tiles_per_block=16)
+    assert default["dense_hits"] == 5 * 4 * 16 * 1024 // 16
+    B.ht_set_tuning(spec, rows=4, group_tiles=32, cand_cap=128, nt_store=2, tiles_per_block=16,
+                    dense_hits=20000)
     try:
         got = B.ht_get_tuning(spec).as_dict()
         assert got == {"rows": 4, "group_tiles": 32, "cand_cap": 128, "nt_store": 2,
-                       "tiles_per_block": 16}
+                       "tiles_per_block": 16, "dense_hits": 20000}
         # the threshold is not part of the key
         other = synth.GridSpec(4, 16, 1024, 1024, threshold=3)
         assert B.ht_get_tuning(other).as_dict() == got
@@ -144,6 +147,9 @@ def test_tuning_validated_and_applied_on_host(lib):
         B.ht_set_tuning(spec, rows=2)
         got = B.ht_get_tuning(spec).as_dict()
         assert got["rows"] == 2 and got["group_tiles"] == default["group_tiles"]
+        assert got["dense_hits"] == default["dense_hits"]
+        B.ht_set_tuning(spec, dense_hits=-1)
+        assert B.ht_get_tuning(spec).dense_hits == -1
     finally:
         B.ht_set_tuning(spec)
     assert B.ht_get_tuning(spec).as_dict() == default

@@ -89,13 +89,21 @@ def test_noalloc_equals_fill_peaks_on_two_calls_the_second_smaller(gpu):
 
 def test_noalloc_counting_sort_layout_and_grid_changes(gpu):
     B = gpu
-    # a 40000-hit event of the served workload: its direct lists do not fit the fixed array, so
-    # the call takes the counting sort; then small grids, so the table region is rewritten
-    ev = synth.make_event(3, next(e for e in range(40) if synth.event_size(3, e) == 40000))
-    assert ev.n == 40000
-    say("noalloc: %d hits on the paper grid (counting sort)" % ev.n)
-    na, ref = run_both(B, CFG1, ev)
+    # the 40000-hit event of the served workload (its peaks come from the stencil over the
+    # matrix), then 64000 hits (two events together), whose direct lists do not fit the fixed
+    # array, so the call takes the counting sort; then small grids, so the table region is
+    # rewritten
+    big = synth.make_event(3, next(e for e in range(40) if synth.event_size(3, e) == 40000))
+    assert big.n == 40000
+    say("noalloc: %d hits on the paper grid" % big.n)
+    na, ref = run_both(B, CFG1, big, capacity=1 << 19)
     assert_identical(na, ref, "40k-hit event")
+    more = synth.make_event(3, next(e for e in range(40) if 20000 <= synth.event_size(3, e) <= 30000))
+    ev = synth.Event(np.concatenate([big.x, more.x]), np.concatenate([big.y, more.y]),
+                     np.concatenate([big.z, more.z]))
+    say("noalloc: %d hits on the paper grid (counting sort)" % ev.n)
+    na, ref = run_both(B, CFG1, ev, capacity=1 << 19)
+    assert_identical(na, ref, "%d-hit event" % ev.n)
     for seed in (1, 2):
         e0 = synth.make_event(0, seed)
         say("noalloc: workload-0 event seed %d (%d hits)" % (seed, e0.n))
