@@ -415,6 +415,9 @@ struct Workspace {
   int ev_cap = 0;
   hipEvent_t ev_copied = nullptr;
   hipStream_t capture = nullptr;  // private stream used only to capture batch graphs
+  hipStream_t side = nullptr;     // side stream of split batches (eager launches)
+  hipStream_t capture_side = nullptr;  // side stream of split batches under capture
+  hipEvent_t split_ev[kMaxPieces + 1] = {};
   struct Graph {
     std::vector<unsigned char> key;
     hipGraphExec_t exec;
@@ -598,7 +601,7 @@ int injected_failure(const char* stage)
 }
 
 int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, bool direct,
-                 bool any_pool, bool any_dense, hipStream_t s, bool* prep_enqueued)
+                 bool any_pool, bool any_dense, hipStream_t s, bool* prep_enqueued, const BatchSplit* split)
 {
   EvDesc none;
   std::memset(&none, 0, sizeof(none));
@@ -612,6 +615,31 @@ int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hit
     *prep_enqueued = true;
   }
   if ((rc = injected_failure("fill"))) return rc;
+  const int pieces = split && g.lds_fill ? std::min(split->pieces, n_ev) : 1;
+  if (pieces > 1) {
+    // The batch in `pieces` runs of consecutive events: the fill of run i + 1 (on s) overlaps
+    // the peak search of run i (on the side stream, after an event recorded when run i's fill
+    // is done): the fill is bound by HBM writes, the candidate test by memory latency. s waits
+    // for the side stream at the end, so the call's completion on s covers everything.
+    hipError_t e;
+    for (int i = 0; i < pieces; ++i) {
+      const int e0 = (int)((int64_t)n_ev * i / pieces), e1 = (int)((int64_t)n_ev * (i + 1) / pieces);
+      if ((rc = check_launch(launch_fill(g, none, d_ev + e0, e1 - e0, true, max_hits, s), "fill launch")))
+        return rc;
+      if ((e = hipEventRecord(split->filled[i], s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
+      if ((e = hipStreamWaitEvent(split->side, split->filled[i], 0)) != hipSuccess)
+        return fail_hip(e, "hipStreamWaitEvent");
+      if (i == 0 && (rc = injected_failure("peaks"))) return rc;
+      if (any_pool && (rc = check_launch(launch_peaks(g, none, d_ev + e0, e1 - e0, split->side), "peak launch")))
+        return rc;
+      if (any_dense &&
+          (rc = check_launch(launch_peaks_dense(g, none, d_ev + e0, e1 - e0, split->side), "stencil peak launch")))
+        return rc;
+    }
+    if ((e = hipEventRecord(split->done, split->side)) != hipSuccess) return fail_hip(e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(s, split->done, 0)) != hipSuccess) return fail_hip(e, "hipStreamWaitEvent");
+    return HT_OK;
+  }
   if (g.lds_fill) {
     StageTimer t("fill", s);
     if ((rc = check_launch(launch_fill(g, none, d_ev, n_ev, true, max_hits, s), "fill launch"))) return rc;
@@ -884,15 +912,33 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
   while (blocks * 256 < max_hits) blocks *= 2;
   const int64_t max_hits_b = max_hits > 0 ? blocks * 256 : 0;
   hipError_t e;
+  // overlap of the peak searches with the fills of later events: the batch in `pieces` runs
+  const int pieces = std::max(1, std::min(std::min(env_int("HT_BATCH_PIECES", 1), kMaxPieces), (int)n_events));
+  BatchSplit split;
+  std::memset(&split, 0, sizeof(split));
+  split.pieces = pieces;
+  const bool graph_mode = env_int("HT_BATCH_GRAPH", 1) != 0;
+  if (pieces > 1) {
+    hipStream_t& side = graph_mode ? w->capture_side : w->side;
+    if (!side && (e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking)) != hipSuccess)
+      return fail_hip(e, "hipStreamCreate(side)");
+    for (int i = 0; i <= kMaxPieces; ++i)
+      if (!w->split_ev[i] && (e = hipEventCreateWithFlags(&w->split_ev[i], hipEventDisableTiming)) != hipSuccess)
+        return fail_hip(e, "hipEventCreate(split)");
+    split.side = side;
+    for (int i = 0; i < kMaxPieces; ++i) split.filled[i] = w->split_ev[i];
+    split.done = w->split_ev[kMaxPieces];
+  }
   // The descriptors above hold this call's counter arrays. The next call switches to the other
   // arrays only once this call's preparation (which counts into these and clears those) is on
   // the stream; a call that fails before that leaves the counters as they were.
-  if (env_int("HT_BATCH_GRAPH", 1) == 0) {
+  if (!graph_mode) {
     e = hipMemcpyAsync(w->d_ev, w->h_ev, sizeof(EvDesc) * n_events, hipMemcpyHostToDevice, p.s);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(descriptors)");
     if ((e = hipEventRecord(w->ev_copied, p.s)) != hipSuccess) return fail_hip(e, "hipEventRecord");
     bool prep_enqueued = false;
-    rc = launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, any_pool, any_dense, p.s, &prep_enqueued);
+    rc = launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, any_pool, any_dense, p.s, &prep_enqueued,
+                      pieces > 1 ? &split : nullptr);
     if (prep_enqueued) flip_counters(w, n_events);
     return rc;
   }
@@ -902,7 +948,8 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
     unsigned char* q = key.data();
     std::memcpy(q, &p.g, sizeof(DevGrid));
     q += sizeof(DevGrid);
-    const int64_t ints[4] = {n_events, max_hits_b, p.dev, (direct ? 1 : 0) | (any_pool ? 2 : 0) | (any_dense ? 4 : 0)};
+    const int64_t ints[4] = {n_events, max_hits_b, p.dev,
+                             (direct ? 1 : 0) | (any_pool ? 2 : 0) | (any_dense ? 4 : 0) | (pieces << 3)};
     std::memcpy(q, ints, sizeof(ints));
     q += sizeof(ints);
     const void* ptrs[2] = {w->d_ev, w->h_ev};
@@ -923,7 +970,7 @@ int ht_fill_peaks_batch(const ht_grid* grid, const ht_event* events, int32_t n_e
     bool captured_prep = false;
     int lrc = e == hipSuccess
                   ? launch_batch(p.g, w->d_ev, n_events, max_hits_b, direct, any_pool, any_dense, w->capture,
-                                 &captured_prep)
+                                 &captured_prep, pieces > 1 ? &split : nullptr)
                   : HT_EDEVICE;
     t_capturing = false;
     hipGraph_t graph = nullptr;

@@ -175,9 +175,19 @@ int make_device_grid(const ht_grid& g, int dev, DevGrid* out);
 // descriptors are already in device memory.
 // *prep_enqueued is set once the preparation (which counts into and clears the events' counter
 // arrays) is on the stream.
+// A batch split into runs of events whose peak searches run on a side stream beside the next
+// run's fill (pieces <= kMaxPieces; pieces 1: no split).
+constexpr int kMaxPieces = 8;
+struct BatchSplit {
+  int pieces;
+  hipStream_t side;
+  hipEvent_t filled[kMaxPieces];  // recorded on the launch stream after each run's fill
+  hipEvent_t done;                // recorded on the side stream after the last peak search
+};
 // any_pool / any_dense: whether some event searches its peaks through the candidate pool /
-// the stencil (only the kernels needed are launched).
+// the stencil (only the kernels needed are launched). split: NULL, or how to overlap.
 int launch_batch(const DevGrid& g, const EvDesc* d_ev, int n_ev, int64_t max_hits, bool direct,
-                 bool any_pool, bool any_dense, hipStream_t s, bool* prep_enqueued);
+                 bool any_pool, bool any_dense, hipStream_t s, bool* prep_enqueued,
+                 const BatchSplit* split = nullptr);
 
 }  // namespace ht

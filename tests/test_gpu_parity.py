@@ -38,7 +38,8 @@ def gpu():
 
 @pytest.fixture()
 def env_tiling():
-    keys = ("HT_FILL_ROWS", "HT_CAND_CAP", "HT_FILL_LDS_BYTES", "HT_BATCH_GRAPH", "HT_POOL_BOUND")
+    keys = ("HT_FILL_ROWS", "HT_CAND_CAP", "HT_FILL_LDS_BYTES", "HT_BATCH_GRAPH", "HT_POOL_BOUND",
+            "HT_BATCH_PIECES", "HT_DENSE_HITS")
     saved = {k: os.environ.get(k) for k in keys}
     yield
     for k, v in saved.items():
@@ -364,6 +365,29 @@ def test_batch_graph_replays_match_eager(gpu, env_tiling):
             for res in (g_res, e_res):
                 c, v, n = res.peaks[i]
                 assert n == on and np.array_equal(c, oc[:64]) and np.array_equal(v, ov[:64])
+
+
+@pytest.mark.parametrize("pieces,graph", [(2, True), (3, False), (8, True)])
+def test_batch_split_into_overlapping_runs(gpu, env_tiling, pieces, graph):
+    """HT_BATCH_PIECES: the batch's fills in runs, each run's peak search on a side stream beside
+    the next run's fill (candidate pool and stencil events mixed), against the oracle."""
+    B = gpu
+    os.environ["HT_BATCH_PIECES"] = str(pieces)
+    os.environ["HT_BATCH_GRAPH"] = "1" if graph else "0"
+    os.environ["HT_DENSE_HITS"] = "200"  # the 250-hit events take the stencil, trimmed ones the pool
+    hits = []
+    for e in range(11):
+        ev = synth.make_event(0, 700 + e)
+        k = [ev.n, 150, 0, ev.n - 20][e % 4]
+        hits.append((ev.x[:k], ev.y[:k], ev.z[:k]))
+    say("batch in %d runs (%s)" % (pieces, "graph" if graph else "eager"))
+    res = B.fill_peaks_batch(CFG0, hits, capacity=256)
+    accs = B.as_u32(res.acc)
+    for i, (x, y, z) in enumerate(hits):
+        M, votes, oc, ov, on = oracle_run(CFG0, x, y, z)
+        assert np.array_equal(accs[i], M), i
+        c, v, n = res.peaks[i]
+        assert n == on and np.array_equal(c, oc) and np.array_equal(v, ov), i
 
 
 def test_batch_of_uneven_paper_sized_events(gpu):
