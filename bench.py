@@ -548,6 +548,45 @@ def bench_crowded(B, torch, synth, steps, tuning=None):
     return res
 
 
+def bench_crossover(B, torch, synth, steps):
+    """The whole fused call (prep, fill, peak search) on served-stream events of 6k-40k hits
+    (workload 3, paper grid), once with every event's peaks from the candidate pool and once
+    from the stencil over the matrix: where the library's default threshold between the two
+    comes from. Peak counts must agree."""
+    import os
+    spec = synth.WORKLOADS[3].grid
+    sizes = [synth.event_size(3, e) for e in range(300)]
+    cap = 1 << 19
+    acc = B.new_acc(spec)
+    out, nf = B.new_peaks(cap)
+    saved = os.environ.get("HT_DENSE_HITS")
+    rows = []
+    for want in (6000, 9000, 12000, 15000, 18000, 22000, 26000, 30000, 35000, 40000):
+        e = int(np.argmin([abs(n - want) for n in sizes]))
+        ev = synth.make_event(3, e)
+        x, y, z = B.hits_to_device(ev.x, ev.y, ev.z)
+        row = {"hits": ev.n}
+        for mode, val in (("pool", "-1"), ("stencil", "1")):
+            os.environ["HT_DENSE_HITS"] = val
+            for _ in range(3):
+                B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                B.ht_fill_peaks(spec, x, y, z, acc, out, cap, nf)
+            torch.cuda.synchronize()
+            row[mode + "_us"] = round((time.perf_counter() - t0) / steps * 1e6, 1)
+            row[mode + "_peaks"] = int(nf.item())
+        assert row["pool_peaks"] == row["stencil_peaks"]
+        rows.append(row)
+    if saved is None:
+        os.environ.pop("HT_DENSE_HITS", None)
+    else:
+        os.environ["HT_DENSE_HITS"] = saved
+    return {"workload": synth.WORKLOADS[3].name, "default_dense_hits": B.ht_get_tuning(spec).dense_hits,
+            "events": rows}
+
+
 def pinned_tuning(text):
     return [int(v) for v in text.split(",")]
 
@@ -577,11 +616,14 @@ def main():
     ap.add_argument("--crowded", action="store_true",
                     help="stage times on small, median and crowded events of the served stream "
                          "(workload 3) at the --tuning shape or the default; prints one line")
+    ap.add_argument("--crossover", action="store_true",
+                    help="time the fused call on served-stream events of 6k-40k hits with the "
+                         "candidate pool and with the stencil peak search; prints one line")
     ap.add_argument("--only", choices=("batched", "stress", "served"),
                     help="one workload only, for profiles: the batched workload 2 (100 events, "
                          "one graph launch) or the stress workload 4 (16 events) at the launch "
                          "shape the batch autotuner picks, --steps capped at 10 batches; or the "
-                         "served workload 3 at its saturation rate on a short trace; prints one "
+                         "served workload 3 at its saturation rate (1200 events); prints one "
                          "line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -602,6 +644,9 @@ def main():
         print(json.dumps({"crowded": bench_crowded(B, torch, synth, min(args.steps, 50), tuning)}),
               flush=True)
         return
+    if args.crossover:
+        print(json.dumps({"crossover": bench_crossover(B, torch, synth, min(args.steps, 20))}), flush=True)
+        return
     if args.only in ("batched", "stress"):
         wl, n_ev, cap_b = (2, 100, 1 << 13) if args.only == "batched" else (4, 16, 1 << 21)
         B.ht_set_tuning(synth.WORKLOADS[wl].grid, B.Tuning(*pinned_tuning(BATCH_TUNING[args.only])))
@@ -610,7 +655,7 @@ def main():
         return
     if args.only == "served":
         B.ht_set_tuning(synth.WORKLOADS[3].grid, B.Tuning(*pinned_tuning(args.tuning)))
-        res = bench_served(B, torch, synth, n_pool=64, n_warm=50, n_meas=300, rates=(1.0,),
+        res = bench_served(B, torch, synth, n_pool=128, n_warm=200, n_meas=1000, rates=(1.0,),
                            budget_gib=24, max_batch=8, n_streams=2)
         print(json.dumps({"served": res}), flush=True)
         return
