@@ -382,12 +382,14 @@ def bench_transfers(B, torch, synth, spec, sizes=(500, 1000, 2000, 4000, 8000), 
     return res
 
 
-KERNEL_SOURCES = ("ht_device.h", "ht_kernels.hip", "ht_fill_rows.hip")
+# the sources whose text defines the fill kernels (the template, its instantiations and the
+# structures it reads)
+KERNEL_SOURCES = ("ht_internal.h", "ht_device.h", "ht_fill_rows.hip")
 
 
 def kernel_sources_sha256():
-    """SHA-256 over the kernel sources, in a fixed order: counters taken on other sources no
-    longer describe the kernels."""
+    """SHA-256 over the fill kernels' sources, in a fixed order: counters taken on other sources
+    no longer describe the kernels."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:

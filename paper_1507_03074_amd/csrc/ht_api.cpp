@@ -183,25 +183,27 @@ Tiling choose_tiling(const ht_grid& g)
     t.tiles_per_slab = (g.n_a + t.rows - 1) / t.rows;
     t.n_tiles = g.n_theta * g.n_phi * t.tiles_per_slab;
   }
-  // Stencil peak search of crowded events: a workgroup holds W columns of every slab (four
-  // cells per thread, W a multiple of 8, at most 1024 threads: the widest such W, since each
-  // slab row is read in pieces of W cells, and pieces under 128 bytes fetch cache lines partly
-  // and twice, and row-buffer misses dominate: 32 cells at least, so at most 128 slabs) and
-  // walks dense_rows A rows. It needs LDS tiles for the fill and rows of a multiple of 8 cells
-  // (the peak mask is written a byte per eight cells).
-  const int n_slabs = g.n_theta * g.n_phi;
-  int w = ((4096 / n_slabs) / 8) * 8;
-  const int forced_w = env_int("HT_DENSE_W", 0);
-  if (forced_w >= 8 && forced_w % 8 == 0 && (int64_t)forced_w * n_slabs <= 4096) w = forced_w;
-  w = std::min(w, ((g.n_b + 7) / 8) * 8);
-  const int w_min = forced_w > 0 ? 8 : std::min(32, ((g.n_b + 7) / 8) * 8);
-  t.dense_w = (t.lds_fill && g.n_b % 8 == 0 && w >= w_min) ? w : 0;
-  t.dense_rows = std::max(1, std::min(env_int("HT_DENSE_ROWS", 64), 4096));
+  // Stencil peak search of crowded events: a workgroup holds kChunkCells B columns of every
+  // slab, one wave per phi cell with every theta cell in its registers (so at most 16 phi cells
+  // and 4 theta cells), and walks dense_rows A rows (a multiple of 12, its unrolled step loop).
+  // It needs LDS tiles for the fill (whose candidate pass it replaces). By default the segments
+  // are as long as lets every workgroup run at once, two per CU (256 CUs).
+  // One buffer resource spans a row of every theta cell's slab: under 2^31 bytes.
+  const bool st_offsets = ((uint64_t)(g.n_theta - 1) * g.n_phi * g.n_a + 1) * g.n_b * 4 < (1ull << 31);
+  t.dense_w = (t.lds_fill && g.n_theta <= 4 && g.n_phi <= 16 && st_offsets) ? 1 : 0;
+  {
+    const int n_chunks = (g.n_b + kChunkCells - 1) / kChunkCells;
+    const int segs = std::max(1, 512 / n_chunks);
+    int s_rows = (g.n_a + segs - 1) / segs;
+    const int forced = env_int("HT_DENSE_ROWS", 0);
+    if (forced > 0) s_rows = std::min(forced, 4096);
+    t.dense_rows = std::max(12, ((s_rows + 11) / 12) * 12);
+  }
   // default: events with at least 5/16 n_slabs n_b hits, about 0.3 hits per (theta, phi, B)
   // cell, where the stencil's one pass over the matrix measured faster than the candidate pool
   // (on the 4x16x1024x1024 grid: 20480 hits; the pool won up to 18k hits, the stencil from 22k);
   // -1 never
-  int64_t dh = ((int64_t)n_slabs * g.n_b * 5 + 15) / 16;
+  int64_t dh = ((int64_t)g.n_theta * g.n_phi * g.n_b * 5 + 15) / 16;
   const int forced_dh = env_int("HT_DENSE_HITS", 0);
   if (forced_dh != 0) dh = forced_dh;
   if (have && tu.dense_hits != 0) dh = tu.dense_hits;
@@ -341,7 +343,8 @@ size_t pool_entries(const DevGrid& g, int64_t n)
 
 static size_t mask_bytes(const DevGrid& g)
 {
-  return ((size_t)g.n_slabs * (size_t)g.n_a * (size_t)g.n_b + 7) / 8;
+  const size_t n_chunks = ((size_t)g.n_b + kChunkCells - 1) / kChunkCells;
+  return 8 * (size_t)g.n_slabs * (size_t)g.n_a * n_chunks;
 }
 
 size_t event_scratch_bytes(const DevGrid& g, int64_t n, bool direct, int peaks)

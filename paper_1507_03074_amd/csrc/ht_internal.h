@@ -52,8 +52,8 @@ struct DevGrid {
   int32_t phi_sectors;     // 1: phi cells are independent sectors (no phi widening or neighbours)
   int32_t packed_lists;    // 1: always the counting-sort (packed) slab lists, never direct ones
   int32_t test_blocks;     // workgroups per event of the candidate test
-  int32_t dense_w;         // B columns per workgroup of the stencil peak search (0: unavailable)
-  int32_t dense_rows;      // A rows per workgroup of the stencil peak search
+  int32_t dense_w;         // 1: the stencil peak search is available on this grid (0: not)
+  int32_t dense_rows;      // A rows per workgroup of the stencil peak search (a multiple of 12)
   int32_t dense_hits;      // events with at least this many hits take the stencil (0: never)
   const float* a2;         // device [n_a]
   const float* phi_cs;     // device [2 * 2 n_phi] (cos, sin)
@@ -88,8 +88,13 @@ struct EvDesc {
   uint32_t* tile_pk;    // [n_tiles] peaks per tile
   uint32_t* group_pk;   // [n_groups] peaks per group of tiles
   int32_t dense;        // 1: peaks from the stencil over the matrix (crowded events), not the pool
-  uint8_t* pk_mask;     // [cells / 8] peak bits of a dense event, in cell order
+  uint8_t* pk_mask;     // [n_slabs n_a n_chunks] 64-bit words of peak bits of a dense event
+                        // (kChunkCells cells per (row, chunk) word, in cell order)
 };
+
+// B columns tested per wave of the stencil peak search: a wave64 holds them and the cell on
+// either side.
+constexpr int kChunkCells = 62;
 
 // Launch shape of one grid (ht_tuning resolved against the defaults).
 struct Tiling {

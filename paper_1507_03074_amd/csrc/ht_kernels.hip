@@ -683,209 +683,260 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
 
 // ---------------------------------------------------------------------------------------------
 // Peak search of crowded events: an LDS-halo stencil over the whole matrix (one read of it), in
-// place of the candidate pool. A workgroup owns one chunk of W B columns of every (theta, phi)
-// slab and walks down a segment of S A rows; thread (slab, q) holds four consecutive cells of
-// its slab's chunk. The strict maximum under (votes, -index) splits the 80 neighbours of a cell
-// c into those of lower index ("before": slabs of lower index, the row above in its own slab,
-// the cell left of it) and the others ("after"). A before-neighbour w beats c iff w >= v(c),
-// i.e. w + 1 > v(c); an after-neighbour iff w > v(c). So with M(c) the maximum over the after-
-// neighbours of w and over the before-neighbours of w + 1 (absent cells count 0),
-//   c is a peak  iff  v(c) >= T  and  v(c) >= M(c).
-// Per row a the workgroup forms R3(a, b) = the maximum over b-1..b+1 in registers, then
-// W9(a-1, b) = the maximum of R3 over rows a-2..a (the 3 x 3 (A, B) window) into LDS, twice:
-// plain and plus one. The test of row a-1 takes from LDS, for each of the eight neighbour slabs,
-// the plain or the plus-one window maximum, whichever its order relative to the thread's slab
-// asks for (fixed per thread: the addresses are computed once), and its own slab's parts from
-// registers. Cells outside theta, A or B count as zero (or one where a plus one is added, which
-// never decides a test: a tested cell holds at least T >= 1 votes); phi wraps (no phi
-// neighbours with phi sectors). Each row's loads are issued kDenseAhead rows ahead, and the two LDS buffers
-// alternate, so each row needs one barrier. Peaks go to a bit mask of the matrix in cell order
-// (one byte per eight cells, written by one lane), their count per group of tiles to group_pk.
+// place of the candidate pool. A workgroup owns one chunk of kChunkCells B columns of every
+// (theta, phi) slab and walks down a segment of S A rows. Wave p holds phi cell p of every theta
+// cell, so its theta neighbours are in its own registers: lane j holds cell b = base + j - 1 of
+// slab (t, p) for each t, where base = kChunkCells * chunk. Lanes 1..62 are tested; lanes 0 and
+// 63 hold the cells just outside the chunk, so that every tested cell's B neighbours are in the
+// wave (neighbouring chunks overlap by those two cells).
+//
+// The strict maximum under (votes, -index) splits the 80 neighbours of a cell c into those of
+// lower index ("before": theta cell t - 1, the phi cell of lower index in theta cell t, the row
+// above in its own slab, the cell left of it) and the others ("after"). A before-neighbour w
+// beats c iff w >= v(c); an after-neighbour iff w > v(c). With Mb and Ma the maxima over the
+// before- and after-neighbours (absent cells count 0),
+//   c is a peak  iff  v(c) >= T,  v(c) >= Mb + 1  and  v(c) >= Ma.
+// Per row a a wave forms, for each t, R3(a, b) = the maximum over b-1..b+1 (neighbour lanes by
+// DPP wave shifts), then W9(a-1, b) = the maximum of R3 over rows a-2..a (the 3 x 3 (A, B)
+// window), and puts W9 into LDS. After one barrier it reads the W9 of its two phi neighbours,
+// P3 = the maximum of the three phi cells' W9, and tests row a-1: the own slab's parts come from
+// registers, theta cell t - 1 gives P3(t - 1) (before), t + 1 gives P3(t + 1) (after), and each
+// phi neighbour in theta cell t adds 1 when it is a before-neighbour (phi wraps: phi cell 0's
+// left neighbour is the last one, an after-neighbour). With phi sectors there are no phi
+// neighbours, no LDS and no barrier.
+//
+// Rows are read with buffer loads, one resource per slab row: a load past the row's n_b cells,
+// or from a row outside the segment's rows a_beg - 1 .. a_end (or outside the matrix), returns
+// zero without touching memory. Each row is loaded kStAhead rows before its step into a ring of
+// kStAhead + 1 register slots; the step loop is unrolled by kStUnroll = lcm(ring slots, 3), so
+// the ring slot, the three rows of R3 history and the three LDS buffers are all fixed registers
+// and offsets. The test of a row is a ballot; its bits 1..62 are the chunk's peak bits, stored as
+// one 64-bit word per (row, chunk) of the peak mask; their count is kept per theta cell in scalar
+// registers and added to the row's group of tiles once per group.
 // ---------------------------------------------------------------------------------------------
-constexpr int kDenseAhead = 4;
+constexpr int kStAhead = 2;
+constexpr int kStSlots = kStAhead + 2;
+constexpr int kStUnroll = 12;
+static_assert(kStSlots == 4 && kStUnroll % 4 == 0, "ring slots, R3 history and LDS buffers must align");
+// the fourth word of a buffer resource on gfx9-family parts: 32-bit data format, no swizzle
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr uint64_t kTestedLanes = 0x7ffffffffffffffeull;  // lanes 1..62
+constexpr uint32_t kStOutside = 0x80000000u;                // a load offset past every resource
 
 __device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) { return max(a, max(b, c)); }
-
-__global__ __launch_bounds__(1024) void k_peak_dense(DevGrid g, EvDesc ev0, const EvDesc* evs)
+// lane j - 1's value (wave_shr:1; lane 0 gets 0)
+__device__ __forceinline__ uint32_t lane_left(uint32_t v)
 {
-  // two buffers, each [plain W9 of every slab | W9 + 1 of every slab | W zeros]
-  extern __shared__ uint32_t s_lds[];
-  EvDesc e = load_ev(ev0, evs);
-  if (!e.dense) return;  // uniform: this event's peaks come from the candidate pool
-  const int W = g.dense_w, S = g.dense_rows, np = g.n_phi, nsl = g.n_slabs;
-  const uint32_t nb = (uint32_t)g.n_b;
-  const uint32_t plus_ofs = (uint32_t)nsl * (uint32_t)W;
-  const uint32_t zero_ofs = 2u * plus_ofs;
-  const uint32_t buf_words = zero_ofs + (uint32_t)W;
-  for (int i = threadIdx.x; i < W; i += blockDim.x) {
-    s_lds[zero_ofs + i] = 0u;
-    s_lds[buf_words + zero_ofs + i] = 0u;
-  }
-  const int n_chunks = (g.n_b + W - 1) / W;
-  // Workgroups are dealt to the eight XCDs in turn; renumbered so that each XCD takes one
-  // contiguous range (adjacent chunks of the same rows, then the next rows), the cache lines that
-  // neighbouring workgroups share (chunk edges, segment edges) are fetched into one L2. The row
-  // bounds are uniform (read from the first lane), so the row loop and its tests stay scalar.
-  const uint32_t G = gridDim.x;
-  const uint32_t lb = G % 8u ? blockIdx.x : (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u;
-  const int chunk = __builtin_amdgcn_readfirstlane((int)lb % n_chunks);
-  const int a_beg = __builtin_amdgcn_readfirstlane(((int)lb / n_chunks) * S);
-  const int a_end = min(a_beg + S, g.n_a);
-  const int qpr = W / 4;  // quads per slab in a chunk (even: W is a multiple of 8)
-  const int s_raw = (int)threadIdx.x / qpr;
-  const int qi = (int)threadIdx.x - s_raw * qpr;
-  const bool live = s_raw < nsl;
-  const int s = live ? s_raw : 0;
-  const int b0 = chunk * W + 4 * qi;
-  const bool in_row = live && b0 < g.n_b;
-  const int t = s / np, p = s - t * np;
-  // word offsets (within a buffer) of what each of the eight neighbour slabs contributes: the
-  // plain window maximum (after), the plus-one one (before) or zeros (absent)
-  uint32_t nofs[8];
-  {
-    int k = 0;
-#pragma unroll
-    for (int dt = -1; dt <= 1; ++dt)
-#pragma unroll
-      for (int dp = -1; dp <= 1; ++dp) {
-        if (dt == 0 && dp == 0) continue;
-        const int tt = t + dt;
-        const int pp = dp < 0 ? (p == 0 ? np - 1 : p - 1) : (dp > 0 ? (p + 1 == np ? 0 : p + 1) : p);
-        const bool ok = tt >= 0 && tt < g.n_theta && !(g.phi_sectors && dp != 0);
-        const int sn = tt * np + pp;
-        nofs[k++] = ok ? (sn < s ? plus_ofs : 0u) + (uint32_t)sn * (uint32_t)W + 4u * (uint32_t)qi
-                       : zero_ofs + 4u * (uint32_t)qi;
-      }
-  }
-  const uint32_t my_ofs = (uint32_t)s * (uint32_t)W + 4u * (uint32_t)qi;
-  const uint32_t T = g.threshold;
-  // per-lane pointers into row 0 of the slab: the quad (clamped into the row for lanes past a
-  // ragged row end, whose values are never used) and its left and right neighbours (clamped
-  // into the row; masked to zero at the row ends)
-  const int bc = min(b0, g.n_b - 4);
-  const GLOBAL uint32_t* q0 = gp((const uint32_t*)e.acc) + (size_t)s * (size_t)g.n_a * nb + bc;
-  const GLOBAL uint32_t* l0 = q0 + (bc > 0 ? -1 : 0);
-  const GLOBAL uint32_t* h0 = q0 + (bc + 4 < g.n_b ? 4 : 3);
-  const uint32_t lmask = b0 > 0 ? 0xffffffffu : 0u;
-  const uint32_t hmask = b0 + 4 < g.n_b ? 0xffffffffu : 0u;
-  uint8_t* mask = e.pk_mask;
-  const uint32_t rows_log2 = (uint32_t)__ffs(g.rows) - 1u;
-  const uint32_t gt_log2 = (uint32_t)__ffs(g.group_tiles) - 1u;
-  const uint32_t row_cells0 = (uint32_t)s * (uint32_t)g.n_a * nb + (uint32_t)b0;
-  const bool writer = (qi & 1) == 0 && in_row;
-  const uint32_t tile0 = (uint32_t)s * (uint32_t)g.tiles_per_slab;
-  // R3 of rows a-2 and a-1, the cells of row a-1 and the cells left and right of them
-  uint32_t rm2[4] = {0u, 0u, 0u, 0u}, rm1[4] = {0u, 0u, 0u, 0u}, vm1[4] = {0u, 0u, 0u, 0u};
-  uint32_t lm1 = 0u, hm1 = 0u;
-  uint32_t buf = 0u;
-
-  // row a (uniform) of the thread's quad and its two neighbours
-#define HT_DENSE_LOAD(a_, v_, l_, h_)                                                          \
-  do {                                                                                         \
-    const size_t ro_ = (size_t)(a_) * nb;                                                      \
-    const u32x4 w_ = *reinterpret_cast<const GLOBAL u32x4*>(q0 + ro_);                         \
-    (v_)[0] = w_.x;                                                                            \
-    (v_)[1] = w_.y;                                                                            \
-    (v_)[2] = w_.z;                                                                            \
-    (v_)[3] = w_.w;                                                                            \
-    (l_) = l0[ro_] & lmask;                                                                    \
-    (h_) = h0[ro_] & hmask;                                                                    \
-  } while (0)
-  // Row a_ (cells v_, left l_, right h_; zeros outside the matrix) arrives: its R3 completes W9
-  // of row a_ - 1, which is tested when test_ (uniform); the peak bits of that row go to the
-  // mask, one byte per eight cells (the odd lane's four bits join the even lane's: same slab,
-  // next quad), and their count to the row's group of tiles (rows and group_tiles are powers
-  // of two).
-#define HT_DENSE_STEP(a_, v_, l_, h_, test_)                                                   \
-  do {                                                                                         \
-    uint32_t r_[4];                                                                            \
-    r_[0] = max3u((l_), (v_)[0], (v_)[1]);                                                     \
-    r_[1] = max3u((v_)[0], (v_)[1], (v_)[2]);                                                  \
-    r_[2] = max3u((v_)[1], (v_)[2], (v_)[3]);                                                  \
-    r_[3] = max3u((v_)[2], (v_)[3], (h_));                                                     \
-    if (test_) {                                                                               \
-      uint32_t* B_ = s_lds + buf * buf_words;                                                  \
-      const u32x4 w9_ = {max3u(rm2[0], rm1[0], r_[0]), max3u(rm2[1], rm1[1], r_[1]),           \
-                         max3u(rm2[2], rm1[2], r_[2]), max3u(rm2[3], rm1[3], r_[3])};          \
-      const u32x4 w9p_ = {w9_.x + 1u, w9_.y + 1u, w9_.z + 1u, w9_.w + 1u};                     \
-      if (live) {                                                                              \
-        *reinterpret_cast<u32x4*>(B_ + my_ofs) = w9_;                                          \
-        *reinterpret_cast<u32x4*>(B_ + plus_ofs + my_ofs) = w9p_;                              \
-      }                                                                                        \
-      lds_barrier();                                                                           \
-      uint32_t m_[4];                                                                          \
-      m_[0] = max3u(max(rm2[0], lm1) + 1u, r_[0], max(vm1[1], T));                             \
-      m_[1] = max3u(max(rm2[1], vm1[0]) + 1u, r_[1], max(vm1[2], T));                          \
-      m_[2] = max3u(max(rm2[2], vm1[1]) + 1u, r_[2], max(vm1[3], T));                          \
-      m_[3] = max3u(max(rm2[3], vm1[2]) + 1u, r_[3], max(hm1, T));                             \
-      u32x4 nw_[8];                                                                            \
-      _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_)                                         \
-        nw_[k_] = *reinterpret_cast<const u32x4*>(B_ + nofs[k_]);                              \
-      m_[0] = max3u(m_[0], max3u(nw_[0].x, nw_[1].x, nw_[2].x),                                \
-                    max3u(nw_[3].x, nw_[4].x, max3u(nw_[5].x, nw_[6].x, nw_[7].x)));           \
-      m_[1] = max3u(m_[1], max3u(nw_[0].y, nw_[1].y, nw_[2].y),                                \
-                    max3u(nw_[3].y, nw_[4].y, max3u(nw_[5].y, nw_[6].y, nw_[7].y)));           \
-      m_[2] = max3u(m_[2], max3u(nw_[0].z, nw_[1].z, nw_[2].z),                                \
-                    max3u(nw_[3].z, nw_[4].z, max3u(nw_[5].z, nw_[6].z, nw_[7].z)));           \
-      m_[3] = max3u(m_[3], max3u(nw_[0].w, nw_[1].w, nw_[2].w),                                \
-                    max3u(nw_[3].w, nw_[4].w, max3u(nw_[5].w, nw_[6].w, nw_[7].w)));           \
-      uint32_t nib_ = 0u;                                                                      \
-      _Pragma("unroll") for (int i_ = 0; i_ < 4; ++i_)                                         \
-        nib_ |= vm1[i_] >= m_[i_] ? (1u << i_) : 0u;                                           \
-      nib_ = in_row ? nib_ : 0u;                                                               \
-      buf ^= 1u;                                                                               \
-      const uint32_t hi_ = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)nib_, 0x101, 0xf, 0xf, false); \
-      if (writer) {                                                                            \
-        const uint32_t byte_ = (nib_ | (hi_ << 4)) & 0xffu;                                    \
-        gp(mask)[(row_cells0 + (uint32_t)((a_) - 1) * nb) >> 3] = (uint8_t)byte_;              \
-        if (byte_)                                                                             \
-          gatomic_add(e.group_pk + ((tile0 + ((uint32_t)((a_) - 1) >> rows_log2)) >> gt_log2), \
-                      (uint32_t)__popc(byte_));                                                \
-      }                                                                                        \
-    }                                                                                          \
-    _Pragma("unroll") for (int i_ = 0; i_ < 4; ++i_) {                                         \
-      rm2[i_] = rm1[i_];                                                                       \
-      rm1[i_] = r_[i_];                                                                        \
-      vm1[i_] = (v_)[i_];                                                                      \
-    }                                                                                          \
-    lm1 = (l_);                                                                                \
-    hm1 = (h_);                                                                                \
-  } while (0)
-
-  const uint32_t zq[4] = {0u, 0u, 0u, 0u};
-  // row a_beg - 1 (zeros above the matrix), never tested
-  if (a_beg > 0) {
-    uint32_t v[4], l, h;
-    HT_DENSE_LOAD(a_beg - 1, v, l, h);
-    HT_DENSE_STEP(a_beg - 1, v, l, h, false);
-  } else {
-    HT_DENSE_STEP(a_beg - 1, zq, 0u, 0u, false);
-  }
-  // rows a_beg .. last, all inside the matrix, loaded kDenseAhead at a time; row a tests a - 1
-  const int last = min(a_end, g.n_a - 1);
-  int a = a_beg;
-  for (; a + kDenseAhead - 1 <= last; a += kDenseAhead) {  // uniform
-    uint32_t v[kDenseAhead][4], l[kDenseAhead], h[kDenseAhead];
-#pragma unroll
-    for (int u = 0; u < kDenseAhead; ++u) HT_DENSE_LOAD(a + u, v[u], l[u], h[u]);
-#pragma unroll
-    for (int u = 0; u < kDenseAhead; ++u) HT_DENSE_STEP(a + u, v[u], l[u], h[u], a + u > a_beg);
-  }
-  for (; a <= last; ++a) {  // uniform
-    uint32_t v[4], l, h;
-    HT_DENSE_LOAD(a, v, l, h);
-    HT_DENSE_STEP(a, v, l, h, a > a_beg);
-  }
-  // below the matrix: row n_a is zeros, and tests row n_a - 1
-  if (a_end == g.n_a) HT_DENSE_STEP(g.n_a, zq, 0u, 0u, true);
-#undef HT_DENSE_STEP
-#undef HT_DENSE_LOAD
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, true);
+}
+// lane j + 1's value (wave_shl:1; lane 63 gets 0)
+__device__ __forceinline__ uint32_t lane_right(uint32_t v)
+{
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, true);
 }
 
-// Ordered output of a dense event: one workgroup per group of tiles (a contiguous range of
-// cells); its output offset is the sum of the earlier groups' peak counts. Thread t takes the
-// t-th of 256 equal, contiguous pieces of the group's part of the mask, all loaded at once; one
-// block scan of the pieces' peak counts gives each thread where its peaks go, in cell order.
+// Block b of a grid of G runs on XCD b % 8 (workgroups are dealt to the eight XCDs in turn); the
+// number this returns is a bijection of [0, G) under which XCD x runs one contiguous range of
+// numbers: the first G % 8 XCDs take ceil(G / 8) of them, the others floor(G / 8).
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t G)
+{
+  const uint32_t x = b & 7u, i = b >> 3, q = G >> 3, r = G & 7u;
+  return x < r ? x * (q + 1u) + i : r * (q + 1u) + (x - r) * q + i;
+}
+
+template <int NT, bool SECT>
+__global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, const EvDesc* evs)
+{
+  // two buffers of W9, each [theta cell][16 phi slots][64 lanes]: fixed strides, so every LDS
+  // address is one of three lane addresses plus a constant
+  extern __shared__ uint32_t s_w9[];
+  constexpr uint32_t kTBytes = 16u * 256u, kBufBytes = NT * kTBytes;
+  EvDesc e = load_ev(ev0, evs);
+  if (!e.dense) return;  // uniform: this event's peaks come from the candidate pool
+  const uint32_t nb = (uint32_t)g.n_b;
+  const int na = g.n_a, np = g.n_phi, S = g.dense_rows;
+  const uint32_t lane = threadIdx.x & 63u;
+  const int p = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nch = (int)((nb + kChunkCells - 1) / kChunkCells);
+  // Workgroups are dealt to the eight XCDs in turn; renumbered so that each XCD takes one
+  // contiguous range (adjacent chunks of the same rows, then the next rows), the cache lines that
+  // neighbouring workgroups share (chunk edges overlap by two cells, segment edges by two rows)
+  // are fetched into one L2. The row bounds are uniform (read from the first lane), so the row
+  // loop and its tests stay scalar.
+  const uint32_t lb = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int chunk = __builtin_amdgcn_readfirstlane((int)lb % nch);
+  const int a_beg = __builtin_amdgcn_readfirstlane(((int)lb / nch) * S);
+  const int a_end = min(a_beg + S, na);
+  const uint32_t base = (uint32_t)chunk * kChunkCells;
+  const uint32_t row_bytes = nb * 4u;
+  // The next row to load (row a_beg - 1 first), as a byte address in slab (0, p). One buffer
+  // resource per row covers the NT rows of slabs (0..NT-1, p), theta cell t's row t t_bytes
+  // further (a scalar offset). A lane's offset is its cell's, or kStOutside for cells outside the
+  // row (the cell left of B = 0, cells past n_b), which the range check turns into zeros (with
+  // or without the scalar offset counted in it: kStOutside is past the resource either way), as
+  // it does every load of a row outside the segment's rows a_beg - 1 .. a_end or the matrix (an
+  // empty resource). The address is never dereferenced outside the rows read.
+  const uintptr_t slab_bytes = (uintptr_t)na * row_bytes;
+  const uint32_t t_bytes = (uint32_t)((uintptr_t)np * slab_bytes);  // (NT-1) t_bytes + row_bytes < 2^31
+  const uint32_t span = (uint32_t)(NT - 1) * t_bytes + row_bytes;
+  const bool cell_in = !(base == 0u && lane == 0u) && base + lane - 1u < nb;
+  const uint32_t off = cell_in ? (base + lane - 1u) * 4u : kStOutside;
+  uintptr_t rp = (uintptr_t)e.acc + (uintptr_t)p * slab_bytes + (uintptr_t)a_beg * row_bytes - row_bytes;
+  int ra = a_beg - 1;  // the row of the next load
+  const uint32_t own_a = (uint32_t)p * 256u + 4u * lane;
+  const uint32_t pm_a = (uint32_t)(p == 0 ? np - 1 : p - 1) * 256u + 4u * lane;
+  const uint32_t pq_a = (uint32_t)(p + 1 == np ? 0 : p + 1) * 256u + 4u * lane;
+  // a phi neighbour of lower index is a before-neighbour: +1 (phi cell 0's left one wraps to the
+  // last, an after-neighbour; the last one's right one wraps to 0, a before-neighbour)
+  const uint32_t inc_m = p > 0 ? 1u : 0u, inc_q = p + 1 == np ? 1u : 0u;
+  const uint32_t T = g.threshold;
+  const uint32_t rows_log2 = (uint32_t)__ffs(g.rows) - 1u;
+  const uint32_t gt_log2 = (uint32_t)__ffs(g.group_tiles) - 1u;
+  // the peak-mask word of (slab (t, p), row a, chunk) is ((t np + p) na + a) nch + chunk: mp
+  // follows the tested row of theta cell 0, theta cell t's word is t mt_bytes further
+  char* mp = reinterpret_cast<char*>(e.pk_mask) +
+             8 * (((size_t)p * (size_t)na + (size_t)a_beg) * (size_t)nch + (size_t)chunk);
+  const uint32_t mt_bytes = 8u * (uint32_t)np * (uint32_t)na * (uint32_t)nch;
+  uint32_t cur_g[NT], cnt[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    cur_g[t] = ((uint32_t)(t * np + p) * (uint32_t)g.tiles_per_slab + ((uint32_t)a_beg >> rows_log2)) >> gt_log2;
+    cnt[t] = 0u;
+  }
+  uint32_t ring[kStSlots][NT], hist[4][NT];
+
+  // The next row (rows outside [a_beg - 1, a_end] or the matrix read zeros) into ring slot
+  // slot_ (a constant).
+#define HT_ST_LOAD(slot_)                                                                      \
+  do {                                                                                         \
+    const int nr_ = (ra >= 0 && ra <= a_end && ra < na) ? (int)span : 0;                      \
+    const __amdgpu_buffer_rsrc_t r_ = __builtin_amdgcn_make_buffer_rsrc((void*)rp, 0, nr_, kRsrcWord3); \
+    _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                          \
+      ring[slot_][t_] = __builtin_amdgcn_raw_buffer_load_b32(r_, off, (uint32_t)t_ * t_bytes, 0); \
+    rp += row_bytes;                                                                           \
+    ++ra;                                                                                      \
+  } while (0)
+  // R3 of step kc_'s row (kc_ a constant congruent to the step modulo kStUnroll) into history
+  // slot kc_ % 4
+#define HT_ST_R3(kc_)                                                                          \
+  do {                                                                                         \
+    _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                        \
+      const uint32_t v_ = ring[(kc_) % kStSlots][t_];                                          \
+      hist[(kc_) % 4][t_] = max(max(lane_left(v_), v_), lane_right(v_));                       \
+    }                                                                                          \
+  } while (0)
+  // W9 of step kc_ - 1's row (complete once R3 of step kc_'s row is) into LDS buffer kc_ % 2
+#define HT_ST_W9(kc_)                                                                          \
+  do {                                                                                         \
+    if (!SECT) {                                                                               \
+      char* B_ = reinterpret_cast<char*>(s_w9) + ((kc_) % 2) * kBufBytes;                      \
+      _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                        \
+        *reinterpret_cast<uint32_t*>(B_ + t_ * kTBytes + own_a) =                              \
+            max3u(hist[((kc_) + 2) % 4][t_], hist[((kc_) + 3) % 4][t_], hist[(kc_) % 4][t_]);  \
+    }                                                                                          \
+  } while (0)
+  // Step kb_ + kc_ (kc_ >= 3 a constant, kb_ a multiple of kStUnroll). The phi neighbours' W9 of
+  // step kc_ - 2's row, put into LDS by the step before (and so behind the barrier that ended
+  // it), are read first; R3 of this step's row follows, and its W9 of the row before goes to
+  // LDS; then step kc_ - 2's row is tested, the row kStAhead steps on is loaded into its ring
+  // slot, and a barrier ends the step.
+#define HT_ST_STEP(kc_, kb_)                                                                   \
+  do {                                                                                         \
+    constexpr int ha_ = ((kc_) + 1) % 4, ht_ = ((kc_) + 2) % 4, hb_ = ((kc_) + 3) % 4;          \
+    constexpr int vs_ = ((kc_) + 2) % kStSlots;                                                \
+    uint32_t wm_[NT], wq_[NT], p3_[NT];                                                        \
+    if (!SECT) {                                                                               \
+      const char* Bp_ = reinterpret_cast<const char*>(s_w9) + (((kc_) + 1) % 2) * kBufBytes;   \
+      _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                      \
+        wm_[t_] = *reinterpret_cast<const uint32_t*>(Bp_ + t_ * kTBytes + pm_a);               \
+        wq_[t_] = *reinterpret_cast<const uint32_t*>(Bp_ + t_ * kTBytes + pq_a);               \
+      }                                                                                        \
+    }                                                                                          \
+    HT_ST_R3(kc_);                                                                             \
+    HT_ST_W9(kc_);                                                                             \
+    /* the tested row's own W9: R3 of the rows above (ha_), itself (ht_) and below (hb_) */     \
+    _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                        \
+      const uint32_t w9_ = max3u(hist[ha_][t_], hist[ht_][t_], hist[hb_][t_]);                  \
+      p3_[t_] = SECT ? w9_ : max3u(wm_[t_], w9_, wq_[t_]);                                     \
+    }                                                                                          \
+    const int tr_ = a_beg + (kb_) + (kc_) - 3; /* the tested row */                            \
+    if ((tr_ & (g.rows - 1)) == 0) { /* a tile starts here, perhaps a group of tiles */        \
+      _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                      \
+        const uint32_t gi_ = ((uint32_t)(t_ * np + p) * (uint32_t)g.tiles_per_slab +           \
+                              ((uint32_t)tr_ >> rows_log2)) >> gt_log2;                        \
+        if (gi_ != cur_g[t_]) {                                                                \
+          if (cnt[t_] != 0u && lane == 0u) gatomic_add(e.group_pk + cur_g[t_], cnt[t_]);      \
+          cur_g[t_] = gi_;                                                                     \
+          cnt[t_] = 0u;                                                                        \
+        }                                                                                      \
+      }                                                                                        \
+    }                                                                                          \
+    uint64_t pk_[NT];                                                                          \
+    _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                        \
+      const uint32_t vm_ = ring[vs_][t_];                                                      \
+      uint32_t mb_ = max(lane_left(vm_), hist[ha_][t_]);                                       \
+      uint32_t ma_ = max(lane_right(vm_), hist[hb_][t_]);                                      \
+      if (t_ > 0) mb_ = max(mb_, p3_[t_ > 0 ? t_ - 1 : 0]);                                    \
+      if (t_ + 1 < NT) ma_ = max(ma_, p3_[t_ + 1 < NT ? t_ + 1 : 0]);                          \
+      uint32_t m_ = max3u(mb_ + 1u, ma_, T);                                                   \
+      if (!SECT) m_ = max3u(m_, wm_[t_] + inc_m, wq_[t_] + inc_q);                             \
+      pk_[t_] = __builtin_amdgcn_ballot_w64(vm_ >= m_) & kTestedLanes;                        \
+    }                                                                                          \
+    if (tr_ < na) { /* rows past the matrix (the last segment's) are zeros, not stored */     \
+      /* lane t stores theta cell t's word: one store instruction of NT lanes */               \
+      uint64_t w_ = pk_[0];                                                                    \
+      _Pragma("unroll") for (int t_ = 1; t_ < NT; ++t_) w_ = lane == (uint32_t)t_ ? pk_[t_] : w_; \
+      if (lane < (uint32_t)NT) *reinterpret_cast<GLOBAL uint64_t*>(gp(mp + lane * mt_bytes)) = w_; \
+      _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                        \
+        cnt[t_] += (uint32_t)__builtin_popcountll(pk_[t_]);                                    \
+      mp += 8 * (size_t)nch;                                                                   \
+    }                                                                                          \
+    HT_ST_LOAD(vs_);                                                                           \
+    if (!SECT) lds_barrier();                                                                  \
+  } while (0)
+
+  // steps 0, 1 and 2 (rows a_beg - 1, a_beg and a_beg + 1) start the R3 history; step 2 puts
+  // W9 of row a_beg into LDS
+#pragma unroll
+  for (int k = 0; k < kStAhead; ++k) HT_ST_LOAD(k);
+  HT_ST_R3(0);
+  HT_ST_LOAD(kStAhead % kStSlots);
+  HT_ST_R3(1);
+  HT_ST_LOAD((1 + kStAhead) % kStSlots);
+  HT_ST_R3(2);
+  HT_ST_W9(2);
+  HT_ST_LOAD((2 + kStAhead) % kStSlots);
+  if (!SECT) lds_barrier();
+  // steps 3 .. S + 2 test rows a_beg .. a_beg + S - 1 (S is a multiple of kStUnroll)
+  for (int kb = 0; kb < S; kb += kStUnroll) {  // uniform
+    HT_ST_STEP(3, kb);
+    HT_ST_STEP(4, kb);
+    HT_ST_STEP(5, kb);
+    HT_ST_STEP(6, kb);
+    HT_ST_STEP(7, kb);
+    HT_ST_STEP(8, kb);
+    HT_ST_STEP(9, kb);
+    HT_ST_STEP(10, kb);
+    HT_ST_STEP(11, kb);
+    HT_ST_STEP(12, kb);
+    HT_ST_STEP(13, kb);
+    HT_ST_STEP(14, kb);
+  }
+#undef HT_ST_STEP
+#undef HT_ST_W9
+#undef HT_ST_R3
+#undef HT_ST_LOAD
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+    if (cnt[t] != 0u && lane == 0u) gatomic_add(e.group_pk + cur_g[t], cnt[t]);
+}
+
+// Ordered output of a dense event: one workgroup per group of tiles (a contiguous range of rows
+// of the matrix, so of peak-mask words); its output offset is the sum of the earlier groups'
+// peak counts. Thread t takes the t-th of 256 equal, contiguous pieces of the group's words, all
+// loaded at once; one block scan of the pieces' peak counts gives each thread where its peaks
+// go, in cell order (words in row, then chunk order; bits 1..62 of a word are the chunk's cells
+// in B order).
 __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   __shared__ uint32_t smem[32];
@@ -911,57 +962,58 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
   uint32_t c_beg, L0, c_last, L1;
   tile_range(g, t0, &c_beg, &L0);
   tile_range(g, t0 + nt - 1, &c_last, &L1);
-  // the group's cells are [c_beg, c_last + L1), every bound a multiple of 8 (n_b is); the
-  // thread's piece is bytes [b_lo, b_hi) of the mask, in whole 32-bit words when aligned
-  const uint64_t by0 = c_beg >> 3, by1 = ((uint64_t)c_last + L1) >> 3;
-  const uint64_t per = (((by1 - by0) + kBlock - 1) / kBlock + 3) & ~(uint64_t)3;  // multiple of 4
-  const uint64_t b_lo = min(by1, by0 + per * threadIdx.x), b_hi = min(by1, b_lo + per);
-  const GLOBAL uint8_t* mask = gp((const uint8_t*)e.pk_mask);
-  const bool words = (by0 & 3u) == 0 && (by1 & 3u) == 0;  // uniform
-  constexpr int kMaxWords = 16;  // up to 64 bytes (512 cells) per thread held in registers
-  uint32_t wv[kMaxWords];
+  const uint32_t nb = (uint32_t)g.n_b, nch = (nb + kChunkCells - 1) / kChunkCells;
+  // the group's rows [c_beg / nb, (c_last + L1) / nb) of the slab-major row order, so its words
+  const uint32_t w0 = (c_beg / nb) * nch, w1 = (uint32_t)(((uint64_t)c_last + L1) / nb) * nch;
+  const uint32_t per = (w1 - w0 + kBlock - 1) / kBlock;
+  const uint32_t lo = min(w1, w0 + per * threadIdx.x), hi = min(w1, lo + per);
+  const GLOBAL uint64_t* mw = reinterpret_cast<const GLOBAL uint64_t*>(gp((const uint8_t*)e.pk_mask));
+  constexpr int kMaxW = 16;  // up to 16 words per thread held in registers
+  uint64_t wv[kMaxW];
   uint32_t cnt = 0;
-  const int nw = (int)((b_hi - b_lo + 3) / 4);
-  if (words && per <= 4 * kMaxWords) {  // uniform
-    const GLOBAL uint32_t* m32 = reinterpret_cast<const GLOBAL uint32_t*>(mask + b_lo);
+  const int nw = (int)(hi - lo);
+  if (per <= (uint32_t)kMaxW) {  // uniform
 #pragma unroll
-    for (int k = 0; k < kMaxWords; ++k) wv[k] = k < nw ? m32[k] : 0u;
+    for (int k = 0; k < kMaxW; ++k) wv[k] = k < nw ? mw[lo + k] : 0ull;
 #pragma unroll
-    for (int k = 0; k < kMaxWords; ++k) cnt += (uint32_t)__popc(wv[k]);
+    for (int k = 0; k < kMaxW; ++k) cnt += (uint32_t)__builtin_popcountll(wv[k]);
   } else {
-    for (uint64_t b = b_lo; b < b_hi; ++b) cnt += (uint32_t)__popc(mask[b]);
+    for (uint32_t w = lo; w < hi; ++w) cnt += (uint32_t)__builtin_popcountll(mw[w]);
   }
   uint32_t tot;
   int64_t o = base + block_excl_scan(cnt, smem, &tot);
   if (o >= e.cap || cnt == 0) return;
-  if (words && per <= 4 * kMaxWords) {  // uniform
+  // cell of bit j of word w: row w / nch, chunk w % nch, B = chunk * kChunkCells + j - 1. The
+  // votes of up to four peaks are loaded together before they are stored.
+#define HT_EMIT_WORD(w_, bits_)                                                                \
+  do {                                                                                         \
+    uint64_t b_ = (bits_);                                                                     \
+    if (b_) {                                                                                  \
+      const uint32_t row_ = (w_) / nch;                                                        \
+      const uint32_t c0_ = row_ * nb + ((w_) - row_ * nch) * kChunkCells - 1u;                 \
+      while (b_) {                                                                             \
+        uint32_t c_[4], v_[4];                                                                 \
+        int n_ = 0;                                                                            \
+        _Pragma("unroll") for (int q_ = 0; q_ < 4; ++q_) {                                     \
+          c_[q_] = c0_ + (b_ ? (uint32_t)__builtin_ctzll(b_) : 1u);                            \
+          n_ += b_ ? 1 : 0;                                                                    \
+          b_ &= b_ - 1ull;                                                                     \
+        }                                                                                      \
+        _Pragma("unroll") for (int q_ = 0; q_ < 4; ++q_) v_[q_] = gp(e.acc)[c_[q_]];          \
+        _Pragma("unroll") for (int q_ = 0; q_ < 4; ++q_) {                                     \
+          if (q_ < n_ && o < e.cap) st_peak(e.out, o, c_[q_], v_[q_], a8);                     \
+          o += q_ < n_ ? 1 : 0;                                                                \
+        }                                                                                      \
+      }                                                                                        \
+    }                                                                                          \
+  } while (0)
+  if (per <= (uint32_t)kMaxW) {  // uniform
 #pragma unroll
-    for (int k = 0; k < kMaxWords; ++k) {
-      uint32_t bits = wv[k];
-      while (bits) {
-        const int i = __ffs(bits) - 1;
-        bits &= bits - 1u;
-        if (o < e.cap) {
-          const uint32_t c = (uint32_t)((b_lo + 4u * (uint32_t)k) * 8u) + (uint32_t)i;
-          st_peak(e.out, o, c, gp(e.acc)[c], a8);
-        }
-        ++o;
-      }
-    }
+    for (int k = 0; k < kMaxW; ++k) HT_EMIT_WORD(lo + (uint32_t)k, wv[k]);
   } else {
-    for (uint64_t b = b_lo; b < b_hi; ++b) {
-      uint32_t bits = mask[b];
-      while (bits) {
-        const int i = __ffs(bits) - 1;
-        bits &= bits - 1u;
-        if (o < e.cap) {
-          const uint32_t c = (uint32_t)(b * 8u) + (uint32_t)i;
-          st_peak(e.out, o, c, gp(e.acc)[c], a8);
-        }
-        ++o;
-      }
-    }
+    for (uint32_t w = lo; w < hi; ++w) HT_EMIT_WORD(w, mw[w]);
   }
+#undef HT_EMIT_WORD
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1142,16 +1194,29 @@ hipError_t launch_peaks(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, 
 
 int dense_blocks(const DevGrid& g)
 {
-  return ((g.n_b + g.dense_w - 1) / g.dense_w) * ((g.n_a + g.dense_rows - 1) / g.dense_rows);
+  return ((g.n_b + kChunkCells - 1) / kChunkCells) * ((g.n_a + g.dense_rows - 1) / g.dense_rows);
 }
 
 hipError_t launch_peaks_dense(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, int n_ev,
                               hipStream_t s)
 {
-  const int threads = ((g.n_slabs * (g.dense_w / 4) + 63) / 64) * 64;
-  // two buffers of plain and plus-one window maxima of every slab, and a zero row each
-  const size_t lds = 2 * ((size_t)2 * g.n_slabs * g.dense_w + g.dense_w) * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_peak_dense, dim3(dense_blocks(g), n_ev), dim3(threads), lds, s, g, ev0, evs);
+  // one wave per phi cell; two LDS buffers of 16 phi slots of 64 window maxima per theta cell
+  // (none with sectors)
+  const dim3 grid(dense_blocks(g), n_ev), block(64 * g.n_phi);
+  const size_t lds = g.phi_sectors ? 0 : 2 * (size_t)g.n_theta * 16 * 256;
+#define HT_ST_CASE(nt_)                                                                        \
+  case nt_:                                                                                    \
+    if (g.phi_sectors) hipLaunchKernelGGL((k_peak_stencil<nt_, true>), grid, block, 0, s, g, ev0, evs); \
+    else hipLaunchKernelGGL((k_peak_stencil<nt_, false>), grid, block, lds, s, g, ev0, evs);  \
+    break
+  switch (g.n_theta) {
+    HT_ST_CASE(1);
+    HT_ST_CASE(2);
+    HT_ST_CASE(3);
+    HT_ST_CASE(4);
+    default: return hipErrorInvalidValue;  // the tiling offers the stencil for 1-4 theta cells only
+  }
+#undef HT_ST_CASE
   hipLaunchKernelGGL(k_peak_write_dense, dim3(n_groups(g), n_ev), dim3(kBlock), 0, s, g, ev0, evs);
   return hipGetLastError();
 }

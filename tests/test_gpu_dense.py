@@ -2,7 +2,8 @@
 k_peak_write_dense from its peak mask) against the CPU oracle, bit for bit.
 
 The fused fill + peak search takes the stencil for events with at least `dense_hits` hits (by
-default n_slabs * n_b / 8: the 40000-hit served event and the stress events do). HT_DENSE_HITS
+default 5/16 n_slabs n_b: the 40000-hit served event does) on grids of at most 4 theta and 16 phi
+cells. HT_DENSE_HITS
 moves that threshold, so the same kernels are checked here on small and ragged grids, every row
 segment length (HT_DENSE_ROWS), ragged B chunks, one theta cell, three phi cells (the wrap),
 phi sectors, truncated outputs, pinned-host outputs, batches that mix both searches (graph and
@@ -89,9 +90,12 @@ def test_dense_threshold_reported(gpu):
     B = gpu
     t = B.ht_get_tuning(CFG1)
     assert t.dense_hits == 5 * 4 * 16 * 1024 // 16
-    assert B.ht_get_tuning(synth.GridSpec(4, 16, 64, 60)).dense_hits == -1   # n_b % 8 != 0
-    # 256 slabs leave pieces of 16 cells per slab row: too narrow to read well
+    assert B.ht_get_tuning(synth.GridSpec(4, 16, 64, 60)).dense_hits > 0
+    # a wave per phi cell holds every theta cell: at most 16 phi and 4 theta cells
     assert B.ht_get_tuning(synth.WORKLOADS[4].grid).dense_hits == -1
+    assert B.ht_get_tuning(synth.GridSpec(5, 3, 64, 64)).dense_hits == -1
+    assert B.ht_get_tuning(synth.GridSpec(2, 17, 64, 64)).dense_hits == -1
+    assert B.ht_get_tuning(synth.GridSpec(4, 16, 64, 64)).dense_hits > 0
 
 
 def test_dense_workload0_events(gpu, env):
@@ -110,9 +114,14 @@ GRIDS = [
     synth.GridSpec(3, 5, 7, 16, a_min=-1500.0, a_max=1300.0, b_min=-1100.0, b_max=1700.0, threshold=2),
     synth.GridSpec(2, 7, 100, 40, a_min=-999.0, a_max=1234.5, b_min=-1500.0, b_max=2000.0, threshold=3),
     synth.GridSpec(4, 16, 130, 72, threshold=4),        # W = 64: a ragged second chunk of 8
-    synth.GridSpec(5, 3, 257, 1000, threshold=3),       # three phi cells: the wrap is both ways
+    synth.GridSpec(4, 3, 257, 1000, threshold=3),       # three phi cells: the wrap is both ways
+    synth.GridSpec(2, 16, 67, 192, threshold=3),        # sixteen phi cells, full 64-column chunks
     synth.GridSpec(1, 4, 33, 24, threshold=2),          # one theta cell
+    synth.GridSpec(2, 5, 30, 62, threshold=2),          # one full chunk of 62 columns
+    synth.GridSpec(3, 4, 25, 125, threshold=2),         # two full chunks and one column
+    synth.GridSpec(2, 4, 33, 60, threshold=2),          # a row length that is no multiple of 8
     synth.GridSpec(2, 4, 40, 48, threshold=2, phi_sectors=True),
+    synth.GridSpec(4, 2, 50, 130, threshold=2, phi_sectors=True),
     synth.GridSpec(3, 1, 20, 64, threshold=2, phi_sectors=True),
 ]
 
@@ -126,7 +135,7 @@ def test_dense_ragged_grids(gpu, env, spec):
         check(B, spec, x, y, z, "%s seed %d" % (spec.shape, seed))
 
 
-@pytest.mark.parametrize("rows", [1, 3, 7, 64, 4096])
+@pytest.mark.parametrize("rows", [1, 12, 13, 64, 4096])
 def test_dense_row_segments(gpu, env, rows):
     B = gpu
     env["HT_DENSE_HITS"] = "1"
@@ -136,6 +145,23 @@ def test_dense_row_segments(gpu, env, rows):
     check(B, spec, x, y, z, "rows %d" % rows)
     ev = synth.make_event(0, 3)
     check(B, CFG0, ev.x, ev.y, ev.z, "workload 0, rows %d" % rows)
+
+
+@pytest.mark.parametrize("rows,gt", [(1, 16), (2, 64), (4, 32), (64, 16)])
+def test_dense_peak_counts_per_group_of_tiles(gpu, env, rows, gt):
+    """The stencil counts each row's peaks into its group of tiles (the ordered writer's output
+    offsets): at every tile height and group size, including groups that end inside a segment
+    of rows and groups that span two slabs."""
+    B = gpu
+    env["HT_DENSE_HITS"] = "1"
+    for spec in (synth.GridSpec(4, 16, 130, 72, threshold=4), synth.GridSpec(3, 3, 37, 200, threshold=3)):
+        try:
+            B.ht_set_tuning(spec, rows=rows, group_tiles=gt)
+            for seed in range(2):
+                x, y, z = random_hits(100 + seed, 500)
+                check(B, spec, x, y, z, "%s rows %d groups of %d" % (spec.shape, rows, gt))
+        finally:
+            B.ht_set_tuning(spec)
 
 
 def test_dense_paper_events_and_truncation(gpu, env):
