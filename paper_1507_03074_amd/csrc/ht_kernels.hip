@@ -937,9 +937,12 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
 // loaded at once; one block scan of the pieces' peak counts gives each thread where its peaks
 // go, in cell order (words in row, then chunk order; bits 1..62 of a word are the chunk's cells
 // in B order).
+constexpr int kWriteStage = 4096;  // peaks of a group staged in LDS by the dense writer
+
 __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc ev0, const EvDesc* evs)
 {
   __shared__ uint32_t smem[32];
+  __shared__ uint32_t s_cells[kWriteStage];
   EvDesc e = load_ev(ev0, evs);
   if (!e.dense) return;
   const int G = blockIdx.x;
@@ -981,10 +984,54 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
     for (uint32_t w = lo; w < hi; ++w) cnt += (uint32_t)__builtin_popcountll(mw[w]);
   }
   uint32_t tot;
-  int64_t o = base + block_excl_scan(cnt, smem, &tot);
+  const uint32_t lo_pk = block_excl_scan(cnt, smem, &tot);  // the thread's first peak in the group
+  // Cell of bit j of word w: row w / nch, chunk w % nch, B = chunk * kChunkCells + j - 1. A group
+  // of at most kWriteStage peaks (the common case) first lists its cells in LDS, in order; then
+  // every thread loads the votes of every 256th of them at once and stores those peaks, so the
+  // group's vote loads take one round trip whichever threads own the crowded words, and the
+  // stores are contiguous. A larger group emits each thread's peaks itself, loading the votes of
+  // up to four at a time.
+#define HT_FOR_PEAKS(w_, bits_, body_)                                                         \
+  do {                                                                                         \
+    uint64_t b_ = (bits_);                                                                     \
+    if (b_) {                                                                                  \
+      const uint32_t row_ = (w_) / nch;                                                        \
+      const uint32_t c0_ = row_ * nb + ((w_) - row_ * nch) * kChunkCells - 1u;                 \
+      while (b_) {                                                                             \
+        const uint32_t c_ = c0_ + (uint32_t)__builtin_ctzll(b_);                               \
+        b_ &= b_ - 1ull;                                                                       \
+        body_;                                                                                 \
+      }                                                                                        \
+    }                                                                                          \
+  } while (0)
+  if (tot <= (uint32_t)kWriteStage) {  // uniform
+    uint32_t i = lo_pk;
+    if (per <= (uint32_t)kMaxW) {  // uniform
+#pragma unroll
+      for (int k = 0; k < kMaxW; ++k) HT_FOR_PEAKS(lo + (uint32_t)k, wv[k], s_cells[i++] = c_);
+    } else {
+      for (uint32_t w = lo; w < hi; ++w) HT_FOR_PEAKS(w, mw[w], s_cells[i++] = c_);
+    }
+    lds_barrier();
+    constexpr int kRounds = kWriteStage / kBlock;
+    uint32_t c[kRounds], v[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint32_t k = (uint32_t)r * kBlock + threadIdx.x;
+      c[r] = s_cells[k < tot ? k : 0u];
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r)
+      if ((uint32_t)r * kBlock < tot) v[r] = gp(e.acc)[c[r]];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint32_t k = (uint32_t)r * kBlock + threadIdx.x;
+      if (k < tot && base + (int64_t)k < e.cap) st_peak(e.out, base + (int64_t)k, c[r], v[r], a8);
+    }
+    return;
+  }
+  int64_t o = base + (int64_t)lo_pk;
   if (o >= e.cap || cnt == 0) return;
-  // cell of bit j of word w: row w / nch, chunk w % nch, B = chunk * kChunkCells + j - 1. The
-  // votes of up to four peaks are loaded together before they are stored.
 #define HT_EMIT_WORD(w_, bits_)                                                                \
   do {                                                                                         \
     uint64_t b_ = (bits_);                                                                     \
@@ -1014,6 +1061,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
     for (uint32_t w = lo; w < hi; ++w) HT_EMIT_WORD(w, mw[w]);
   }
 #undef HT_EMIT_WORD
+#undef HT_FOR_PEAKS
 }
 
 // ---------------------------------------------------------------------------------------------
