@@ -88,8 +88,8 @@ struct EvDesc {
   uint32_t* tile_pk;    // [n_tiles] peaks per tile
   uint32_t* group_pk;   // [n_groups] peaks per group of tiles
   int32_t dense;        // 1: peaks from the stencil over the matrix (crowded events), not the pool
-  uint8_t* pk_mask;     // [n_slabs n_a n_chunks] 64-bit words of peak bits of a dense event
-                        // (kChunkCells cells per (row, chunk) word, in cell order)
+  uint8_t* pk_mask;     // 64-bit words of peak bits of a dense event, kChunkCells cells per
+                        // (slab, row, chunk) word, stored by the stencil's workgroups
 };
 
 // B columns tested per wave of the stencil peak search: a wave64 holds them and the cell on

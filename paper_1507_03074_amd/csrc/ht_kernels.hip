@@ -714,10 +714,10 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
 // one 64-bit word per (row, chunk) of the peak mask; their count is kept per theta cell in scalar
 // registers and added to the row's group of tiles once per group.
 // ---------------------------------------------------------------------------------------------
-constexpr int kStAhead = 2;
-constexpr int kStSlots = kStAhead + 2;
+constexpr int kStAhead = 3;
+constexpr int kStSlots = kStAhead + 1;
 constexpr int kStUnroll = 12;
-static_assert(kStSlots == 4 && kStUnroll % 4 == 0, "ring slots, R3 history and LDS buffers must align");
+static_assert(kStUnroll % kStSlots == 0 && kStUnroll % 3 == 0, "ring slots, R3 history and LDS buffers must align");
 // the fourth word of a buffer resource on gfx9-family parts: 32-bit data format, no swizzle
 constexpr int kRsrcWord3 = 0x00020000;
 constexpr uint64_t kTestedLanes = 0x7ffffffffffffffeull;  // lanes 1..62
@@ -786,24 +786,30 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
   const uint32_t own_a = (uint32_t)p * 256u + 4u * lane;
   const uint32_t pm_a = (uint32_t)(p == 0 ? np - 1 : p - 1) * 256u + 4u * lane;
   const uint32_t pq_a = (uint32_t)(p + 1 == np ? 0 : p + 1) * 256u + 4u * lane;
-  // a phi neighbour of lower index is a before-neighbour: +1 (phi cell 0's left one wraps to the
-  // last, an after-neighbour; the last one's right one wraps to 0, a before-neighbour)
-  const uint32_t inc_m = p > 0 ? 1u : 0u, inc_q = p + 1 == np ? 1u : 0u;
+  const bool p_mid = p > 0 && p + 1 < np;  // phi neighbours: one before, one after
   const uint32_t T = g.threshold;
   const uint32_t rows_log2 = (uint32_t)__ffs(g.rows) - 1u;
   const uint32_t gt_log2 = (uint32_t)__ffs(g.group_tiles) - 1u;
-  // the peak-mask word of (slab (t, p), row a, chunk) is ((t np + p) na + a) nch + chunk: mp
-  // follows the tested row of theta cell 0, theta cell t's word is t mt_bytes further
-  char* mp = reinterpret_cast<char*>(e.pk_mask) +
-             8 * (((size_t)p * (size_t)na + (size_t)a_beg) * (size_t)nch + (size_t)chunk);
-  const uint32_t mt_bytes = 8u * (uint32_t)np * (uint32_t)na * (uint32_t)nch;
+  // Peak words are stored workgroup by workgroup: workgroup lb's region holds S NT words per
+  // phi cell, [phi cell][row of the segment][theta cell], so that each wave writes one
+  // contiguous run. A wave's words wait in its own LDS staging slots, [step of the block][theta
+  // cell] after the W9 buffers, and go out once per block of kStUnroll steps: one store of
+  // kStUnroll NT contiguous words per wave (a store per step, or scattered stores, each of part
+  // of a cache line, are slow to complete, and each is waited for with the next row's loads).
+  GLOBAL uint64_t* mw = reinterpret_cast<GLOBAL uint64_t*>(gp(e.pk_mask)) +
+                        ((size_t)lb * (size_t)np + (size_t)p) * (size_t)S * NT;
+  constexpr uint32_t kStageStep = NT * 8u;  // bytes per step in a wave's slots
+  char* const stage_w = reinterpret_cast<char*>(s_w9) + (SECT ? 0u : 2u * kBufBytes) +
+                        (uint32_t)p * (kStUnroll * kStageStep);
+  // slot (u, t) is at stage_w + 8 (u NT + t): written by lane 0, read back by lane u NT + t
+  char* const stage = stage_w + 8u * lane;
   uint32_t cur_g[NT], cnt[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     cur_g[t] = ((uint32_t)(t * np + p) * (uint32_t)g.tiles_per_slab + ((uint32_t)a_beg >> rows_log2)) >> gt_log2;
     cnt[t] = 0u;
   }
-  uint32_t ring[kStSlots][NT], hist[4][NT];
+  uint32_t ring[kStSlots][NT], hist[3][NT];
 
   // The next row (rows outside [a_beg - 1, a_end] or the matrix read zeros) into ring slot
   // slot_ (a constant).
@@ -817,49 +823,69 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
     ++ra;                                                                                      \
   } while (0)
   // R3 of step kc_'s row (kc_ a constant congruent to the step modulo kStUnroll) into history
-  // slot kc_ % 4
+  // slot kc_ % 3
 #define HT_ST_R3(kc_)                                                                          \
   do {                                                                                         \
     _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                        \
       const uint32_t v_ = ring[(kc_) % kStSlots][t_];                                          \
-      hist[(kc_) % 4][t_] = max(max(lane_left(v_), v_), lane_right(v_));                       \
+      hist[(kc_) % 3][t_] = max(max(lane_left(v_), v_), lane_right(v_));                       \
     }                                                                                          \
   } while (0)
-  // W9 of step kc_ - 1's row (complete once R3 of step kc_'s row is) into LDS buffer kc_ % 2
-#define HT_ST_W9(kc_)                                                                          \
+  // The test of the row in ring slot vs_ (R3 above in h0_, below in h2_) for every theta cell.
+  // Its phi neighbours in the own theta cell join the before- or after-neighbours by the wave's
+  // class c_ (a constant; uniform per wave): 0 phi cells 1 .. n_phi - 2 (phi - 1 before, phi + 1
+  // after; also sectors, which have none), 1 phi cell 0 (both after: phi - 1 wraps to the last),
+  // 2 the last phi cell (both before: phi + 1 wraps to 0).
+#define HT_ST_TEST(c_)                                                                         \
   do {                                                                                         \
+    _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                        \
+      const uint32_t vm_ = ring[vs_][t_];                                                      \
+      uint32_t mb_ = max(lane_left(vm_), hist[h0_][t_]);                                       \
+      uint32_t ma_ = max(lane_right(vm_), hist[h2_][t_]);                                      \
+      const uint32_t pb_ = t_ > 0 ? p3_[t_ > 0 ? t_ - 1 : 0] : 0u;                             \
+      const uint32_t pa_ = t_ + 1 < NT ? p3_[t_ + 1 < NT ? t_ + 1 : 0] : 0u;                   \
+      if (SECT) {                                                                              \
+        mb_ = max(mb_, pb_);                                                                   \
+        ma_ = max(ma_, pa_);                                                                   \
+      } else if ((c_) == 0) {                                                                  \
+        mb_ = max3u(mb_, pb_, wm_[t_]);                                                        \
+        ma_ = max3u(ma_, pa_, wq_[t_]);                                                        \
+      } else if ((c_) == 1) {                                                                  \
+        mb_ = max(mb_, pb_);                                                                   \
+        ma_ = max3u(ma_, pa_, max(wm_[t_], wq_[t_]));                                          \
+      } else {                                                                                 \
+        mb_ = max3u(mb_, pb_, max(wm_[t_], wq_[t_]));                                          \
+        ma_ = max(ma_, pa_);                                                                   \
+      }                                                                                        \
+      pk_[t_] = __builtin_amdgcn_ballot_w64(vm_ >= max3u(mb_ + 1u, ma_, T)) & kTestedLanes;   \
+    }                                                                                          \
+  } while (0)
+  // Step kb_ + kc_ (kc_ >= 2 a constant, kb_ a multiple of kStUnroll): R3 of its row completes W9
+  // of the row before; W9 goes to LDS buffer kc_ % 2, and after one barrier the phi neighbours'
+  // are read and the row before is tested; then the row kStAhead steps on is loaded into the
+  // slot of that tested row.
+#define HT_ST_STEP(kc_, kb_)                                                                   \
+  do {                                                                                         \
+    HT_ST_R3(kc_);                                                                             \
+    constexpr int h0_ = ((kc_) + 1) % 3, h1_ = ((kc_) + 2) % 3, h2_ = (kc_) % 3;               \
+    constexpr int vs_ = ((kc_) + kStSlots - 1) % kStSlots;                                     \
+    uint32_t w9_[NT], p3_[NT], wm_[NT], wq_[NT];                                               \
+    _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                          \
+      w9_[t_] = max3u(hist[h0_][t_], hist[h1_][t_], hist[h2_][t_]);                            \
     if (!SECT) {                                                                               \
       char* B_ = reinterpret_cast<char*>(s_w9) + ((kc_) % 2) * kBufBytes;                      \
       _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                        \
-        *reinterpret_cast<uint32_t*>(B_ + t_ * kTBytes + own_a) =                              \
-            max3u(hist[((kc_) + 2) % 4][t_], hist[((kc_) + 3) % 4][t_], hist[(kc_) % 4][t_]);  \
-    }                                                                                          \
-  } while (0)
-  // Step kb_ + kc_ (kc_ >= 3 a constant, kb_ a multiple of kStUnroll). The phi neighbours' W9 of
-  // step kc_ - 2's row, put into LDS by the step before (and so behind the barrier that ended
-  // it), are read first; R3 of this step's row follows, and its W9 of the row before goes to
-  // LDS; then step kc_ - 2's row is tested, the row kStAhead steps on is loaded into its ring
-  // slot, and a barrier ends the step.
-#define HT_ST_STEP(kc_, kb_)                                                                   \
-  do {                                                                                         \
-    constexpr int ha_ = ((kc_) + 1) % 4, ht_ = ((kc_) + 2) % 4, hb_ = ((kc_) + 3) % 4;          \
-    constexpr int vs_ = ((kc_) + 2) % kStSlots;                                                \
-    uint32_t wm_[NT], wq_[NT], p3_[NT];                                                        \
-    if (!SECT) {                                                                               \
-      const char* Bp_ = reinterpret_cast<const char*>(s_w9) + (((kc_) + 1) % 2) * kBufBytes;   \
+        *reinterpret_cast<uint32_t*>(B_ + t_ * kTBytes + own_a) = w9_[t_];                     \
+      lds_barrier();                                                                           \
       _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                      \
-        wm_[t_] = *reinterpret_cast<const uint32_t*>(Bp_ + t_ * kTBytes + pm_a);               \
-        wq_[t_] = *reinterpret_cast<const uint32_t*>(Bp_ + t_ * kTBytes + pq_a);               \
+        wm_[t_] = *reinterpret_cast<const uint32_t*>(B_ + t_ * kTBytes + pm_a);                \
+        wq_[t_] = *reinterpret_cast<const uint32_t*>(B_ + t_ * kTBytes + pq_a);                \
+        p3_[t_] = max3u(wm_[t_], w9_[t_], wq_[t_]);                                            \
       }                                                                                        \
+    } else {                                                                                   \
+      _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) p3_[t_] = wm_[t_] = wq_[t_] = w9_[t_]; \
     }                                                                                          \
-    HT_ST_R3(kc_);                                                                             \
-    HT_ST_W9(kc_);                                                                             \
-    /* the tested row's own W9: R3 of the rows above (ha_), itself (ht_) and below (hb_) */     \
-    _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                        \
-      const uint32_t w9_ = max3u(hist[ha_][t_], hist[ht_][t_], hist[hb_][t_]);                  \
-      p3_[t_] = SECT ? w9_ : max3u(wm_[t_], w9_, wq_[t_]);                                     \
-    }                                                                                          \
-    const int tr_ = a_beg + (kb_) + (kc_) - 3; /* the tested row */                            \
+    const int tr_ = a_beg + (kb_) + (kc_) - 2; /* the tested row */                            \
     if ((tr_ & (g.rows - 1)) == 0) { /* a tile starts here, perhaps a group of tiles */        \
       _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                      \
         const uint32_t gi_ = ((uint32_t)(t_ * np + p) * (uint32_t)g.tiles_per_slab +           \
@@ -872,43 +898,30 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
       }                                                                                        \
     }                                                                                          \
     uint64_t pk_[NT];                                                                          \
-    _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                        \
-      const uint32_t vm_ = ring[vs_][t_];                                                      \
-      uint32_t mb_ = max(lane_left(vm_), hist[ha_][t_]);                                       \
-      uint32_t ma_ = max(lane_right(vm_), hist[hb_][t_]);                                      \
-      if (t_ > 0) mb_ = max(mb_, p3_[t_ > 0 ? t_ - 1 : 0]);                                    \
-      if (t_ + 1 < NT) ma_ = max(ma_, p3_[t_ + 1 < NT ? t_ + 1 : 0]);                          \
-      uint32_t m_ = max3u(mb_ + 1u, ma_, T);                                                   \
-      if (!SECT) m_ = max3u(m_, wm_[t_] + inc_m, wq_[t_] + inc_q);                             \
-      pk_[t_] = __builtin_amdgcn_ballot_w64(vm_ >= m_) & kTestedLanes;                        \
+    if (SECT || p_mid) HT_ST_TEST(0);                                                          \
+    else if (p == 0) HT_ST_TEST(1);                                                            \
+    else HT_ST_TEST(2);                                                                        \
+    if (lane == 0u) { /* lane 0 puts the words into the wave's staging slots */               \
+      _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                        \
+        *reinterpret_cast<uint64_t*>(stage + ((kc_) - 2) * kStageStep + 8 * t_) = pk_[t_];     \
     }                                                                                          \
-    if (tr_ < na) { /* rows past the matrix (the last segment's) are zeros, not stored */     \
-      /* lane t stores theta cell t's word: one store instruction of NT lanes */               \
-      uint64_t w_ = pk_[0];                                                                    \
-      _Pragma("unroll") for (int t_ = 1; t_ < NT; ++t_) w_ = lane == (uint32_t)t_ ? pk_[t_] : w_; \
-      if (lane < (uint32_t)NT) *reinterpret_cast<GLOBAL uint64_t*>(gp(mp + lane * mt_bytes)) = w_; \
+    if (tr_ < na) { /* rows past the matrix (the last segment's) are zeros, not counted */    \
       _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                        \
         cnt[t_] += (uint32_t)__builtin_popcountll(pk_[t_]);                                    \
-      mp += 8 * (size_t)nch;                                                                   \
     }                                                                                          \
     HT_ST_LOAD(vs_);                                                                           \
-    if (!SECT) lds_barrier();                                                                  \
   } while (0)
 
-  // steps 0, 1 and 2 (rows a_beg - 1, a_beg and a_beg + 1) start the R3 history; step 2 puts
-  // W9 of row a_beg into LDS
+  // steps 0 and 1 (rows a_beg - 1 and a_beg) only start the R3 history
 #pragma unroll
   for (int k = 0; k < kStAhead; ++k) HT_ST_LOAD(k);
   HT_ST_R3(0);
   HT_ST_LOAD(kStAhead % kStSlots);
   HT_ST_R3(1);
   HT_ST_LOAD((1 + kStAhead) % kStSlots);
-  HT_ST_R3(2);
-  HT_ST_W9(2);
-  HT_ST_LOAD((2 + kStAhead) % kStSlots);
-  if (!SECT) lds_barrier();
-  // steps 3 .. S + 2 test rows a_beg .. a_beg + S - 1 (S is a multiple of kStUnroll)
+  // steps 2 .. S + 1 test rows a_beg .. a_beg + S - 1 (S is a multiple of kStUnroll)
   for (int kb = 0; kb < S; kb += kStUnroll) {  // uniform
+    HT_ST_STEP(2, kb);
     HT_ST_STEP(3, kb);
     HT_ST_STEP(4, kb);
     HT_ST_STEP(5, kb);
@@ -920,10 +933,15 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
     HT_ST_STEP(11, kb);
     HT_ST_STEP(12, kb);
     HT_ST_STEP(13, kb);
-    HT_ST_STEP(14, kb);
+    // the block's words leave the staging slots: lane u NT + t stores theta cell t's word of the
+    // block's u-th row (a contiguous run of the wave's region). Lane 0 wrote the slots: the
+    // fence keeps these reads after its writes (with phi sectors no barrier orders them).
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+    if (lane < (uint32_t)(kStUnroll * NT))
+      mw[(size_t)kb * NT + lane] = *reinterpret_cast<const uint64_t*>(stage);
   }
 #undef HT_ST_STEP
-#undef HT_ST_W9
+#undef HT_ST_TEST
 #undef HT_ST_R3
 #undef HT_ST_LOAD
 #pragma unroll
@@ -966,22 +984,63 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
   tile_range(g, t0, &c_beg, &L0);
   tile_range(g, t0 + nt - 1, &c_last, &L1);
   const uint32_t nb = (uint32_t)g.n_b, nch = (nb + kChunkCells - 1) / kChunkCells;
-  // the group's rows [c_beg / nb, (c_last + L1) / nb) of the slab-major row order, so its words
+  // The group's rows [c_beg / nb, (c_last + L1) / nb) of the slab-major row order, so its words
+  // in cell order ("logical" words w = (slab n_a + a) nch + chunk). The stencil stored the word
+  // of (slab (t, p), row a = seg S + r, chunk) at [workgroup seg nch + chunk][p][r][t]; a
+  // thread walks its logical words with that position kept up to date.
   const uint32_t w0 = (c_beg / nb) * nch, w1 = (uint32_t)(((uint64_t)c_last + L1) / nb) * nch;
   const uint32_t per = (w1 - w0 + kBlock - 1) / kBlock;
   const uint32_t lo = min(w1, w0 + per * threadIdx.x), hi = min(w1, lo + per);
   const GLOBAL uint64_t* mw = reinterpret_cast<const GLOBAL uint64_t*>(gp((const uint8_t*)e.pk_mask));
+  const uint32_t na = (uint32_t)g.n_a, np = (uint32_t)g.n_phi, nth = (uint32_t)g.n_theta;
+  const uint32_t S = (uint32_t)g.dense_rows;
+  uint32_t ch = lo % nch, a = (lo / nch) % na, sl = lo / nch / na;
+  uint32_t t = sl / np, pp = sl - t * np, seg = a / S, r = a - seg * S;
+  auto rewind = [&]() {
+    ch = lo % nch;
+    a = (lo / nch) % na;
+    sl = lo / nch / na;
+    t = sl / np;
+    pp = sl - t * np;
+    seg = a / S;
+    r = a - seg * S;
+  };
+  auto phys = [&]() { return (((seg * nch + ch) * np + pp) * S + r) * nth + t; };
+  auto next = [&]() {
+    if (++ch == nch) {
+      ch = 0;
+      if (++r == S) {
+        r = 0;
+        ++seg;
+      }
+      if (++a == na) {
+        a = 0;
+        seg = 0;
+        r = 0;
+        if (++pp == np) {
+          pp = 0;
+          ++t;
+        }
+      }
+    }
+  };
   constexpr int kMaxW = 16;  // up to 16 words per thread held in registers
   uint64_t wv[kMaxW];
   uint32_t cnt = 0;
   const int nw = (int)(hi - lo);
   if (per <= (uint32_t)kMaxW) {  // uniform
 #pragma unroll
-    for (int k = 0; k < kMaxW; ++k) wv[k] = k < nw ? mw[lo + k] : 0ull;
+    for (int k = 0; k < kMaxW; ++k) {
+      wv[k] = k < nw ? mw[phys()] : 0ull;
+      next();
+    }
 #pragma unroll
     for (int k = 0; k < kMaxW; ++k) cnt += (uint32_t)__builtin_popcountll(wv[k]);
   } else {
-    for (uint32_t w = lo; w < hi; ++w) cnt += (uint32_t)__builtin_popcountll(mw[w]);
+    for (uint32_t w = lo; w < hi; ++w) {
+      cnt += (uint32_t)__builtin_popcountll(mw[phys()]);
+      next();
+    }
   }
   uint32_t tot;
   const uint32_t lo_pk = block_excl_scan(cnt, smem, &tot);  // the thread's first peak in the group
@@ -1010,7 +1069,11 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
 #pragma unroll
       for (int k = 0; k < kMaxW; ++k) HT_FOR_PEAKS(lo + (uint32_t)k, wv[k], s_cells[i++] = c_);
     } else {
-      for (uint32_t w = lo; w < hi; ++w) HT_FOR_PEAKS(w, mw[w], s_cells[i++] = c_);
+      rewind();
+      for (uint32_t w = lo; w < hi; ++w) {
+        HT_FOR_PEAKS(w, mw[phys()], s_cells[i++] = c_);
+        next();
+      }
     }
     lds_barrier();
     constexpr int kRounds = kWriteStage / kBlock;
@@ -1058,7 +1121,11 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
 #pragma unroll
     for (int k = 0; k < kMaxW; ++k) HT_EMIT_WORD(lo + (uint32_t)k, wv[k]);
   } else {
-    for (uint32_t w = lo; w < hi; ++w) HT_EMIT_WORD(w, mw[w]);
+    rewind();
+    for (uint32_t w = lo; w < hi; ++w) {
+      HT_EMIT_WORD(w, mw[phys()]);
+      next();
+    }
   }
 #undef HT_EMIT_WORD
 #undef HT_FOR_PEAKS
@@ -1249,12 +1316,13 @@ hipError_t launch_peaks_dense(const DevGrid& g, const EvDesc& ev0, const EvDesc*
                               hipStream_t s)
 {
   // one wave per phi cell; two LDS buffers of 16 phi slots of 64 window maxima per theta cell
-  // (none with sectors)
+  // (none with sectors), then every wave's staging slots for 12 steps of peak words
   const dim3 grid(dense_blocks(g), n_ev), block(64 * g.n_phi);
-  const size_t lds = g.phi_sectors ? 0 : 2 * (size_t)g.n_theta * 16 * 256;
+  const size_t lds = (g.phi_sectors ? 0 : 2 * (size_t)g.n_theta * 16 * 256) +
+                     (size_t)g.n_phi * 12 * g.n_theta * 8;
 #define HT_ST_CASE(nt_)                                                                        \
   case nt_:                                                                                    \
-    if (g.phi_sectors) hipLaunchKernelGGL((k_peak_stencil<nt_, true>), grid, block, 0, s, g, ev0, evs); \
+    if (g.phi_sectors) hipLaunchKernelGGL((k_peak_stencil<nt_, true>), grid, block, lds, s, g, ev0, evs); \
     else hipLaunchKernelGGL((k_peak_stencil<nt_, false>), grid, block, lds, s, g, ev0, evs);  \
     break
   switch (g.n_theta) {
