@@ -722,6 +722,7 @@ static_assert(kStUnroll % kStSlots == 0 && kStUnroll % 3 == 0, "ring slots, R3 h
 constexpr int kRsrcWord3 = 0x00020000;
 constexpr uint64_t kTestedLanes = 0x7ffffffffffffffeull;  // lanes 1..62
 constexpr uint32_t kStOutside = 0x80000000u;                // a load offset past every resource
+constexpr int kStWholeRows = 48;  // segments up to this many rows keep all their peak words in LDS
 
 __device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) { return max(a, max(b, c)); }
 // lane j - 1's value (wave_shr:1; lane 0 gets 0)
@@ -792,17 +793,21 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
   const uint32_t gt_log2 = (uint32_t)__ffs(g.group_tiles) - 1u;
   // Peak words are stored workgroup by workgroup: workgroup lb's region holds S NT words per
   // phi cell, [phi cell][row of the segment][theta cell], so that each wave writes one
-  // contiguous run. A wave's words wait in its own LDS staging slots, [step of the block][theta
-  // cell] after the W9 buffers, and go out once per block of kStUnroll steps: one store of
-  // kStUnroll NT contiguous words per wave (a store per step, or scattered stores, each of part
-  // of a cache line, are slow to complete, and each is waited for with the next row's loads).
+  // contiguous run. A wave's words wait in its own LDS staging slots, [row][theta cell] after the
+  // W9 buffers: for the whole segment when it has at most kStWholeRows rows (the default), and
+  // go out at the end; else for a block of kStUnroll rows, and go out after each block. Stores
+  // of peak words are slow to complete, and every one is waited for with the loads of the rows
+  // that follow it, so a wave stores as few times as it can.
   GLOBAL uint64_t* mw = reinterpret_cast<GLOBAL uint64_t*>(gp(e.pk_mask)) +
                         ((size_t)lb * (size_t)np + (size_t)p) * (size_t)S * NT;
-  constexpr uint32_t kStageStep = NT * 8u;  // bytes per step in a wave's slots
+  constexpr uint32_t kStageStep = NT * 8u;  // bytes per row in a wave's slots
+  const bool whole = S <= kStWholeRows;     // uniform
+  const uint32_t slot_rows = whole ? (uint32_t)S : (uint32_t)kStUnroll;
   char* const stage_w = reinterpret_cast<char*>(s_w9) + (SECT ? 0u : 2u * kBufBytes) +
-                        (uint32_t)p * (kStUnroll * kStageStep);
-  // slot (u, t) is at stage_w + 8 (u NT + t): written by lane 0, read back by lane u NT + t
+                        (uint32_t)p * slot_rows * kStageStep;
+  // slot (row u, t) is at stage_w + 8 (u NT + t): written by lane 0, read back by lane u NT + t
   char* const stage = stage_w + 8u * lane;
+  char* stage_blk = stage_w;  // lane 0's slots of the block's first row
   uint32_t cur_g[NT], cnt[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -903,7 +908,7 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
     else HT_ST_TEST(2);                                                                        \
     if (lane == 0u) { /* lane 0 puts the words into the wave's staging slots */               \
       _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                        \
-        *reinterpret_cast<uint64_t*>(stage + ((kc_) - 2) * kStageStep + 8 * t_) = pk_[t_];     \
+        *reinterpret_cast<uint64_t*>(stage_blk + ((kc_) - 2) * kStageStep + 8 * t_) = pk_[t_]; \
     }                                                                                          \
     if (tr_ < na) { /* rows past the matrix (the last segment's) are zeros, not counted */    \
       _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                        \
@@ -933,12 +938,22 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
     HT_ST_STEP(11, kb);
     HT_ST_STEP(12, kb);
     HT_ST_STEP(13, kb);
-    // the block's words leave the staging slots: lane u NT + t stores theta cell t's word of the
-    // block's u-th row (a contiguous run of the wave's region). Lane 0 wrote the slots: the
-    // fence keeps these reads after its writes (with phi sectors no barrier orders them).
+    if (whole) {  // uniform
+      stage_blk += kStUnroll * kStageStep;
+    } else {
+      // the block's words leave the staging slots: lane u NT + t stores theta cell t's word of
+      // the block's u-th row (a contiguous run of the wave's region). Lane 0 wrote the slots:
+      // the fence keeps these reads after its writes (with phi sectors no barrier orders them).
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+      if (lane < (uint32_t)(kStUnroll * NT))
+        mw[(size_t)kb * NT + lane] = *reinterpret_cast<const uint64_t*>(stage);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+    }
+  }
+  if (whole) {  // uniform: the segment's words, S NT of them, in runs of 64
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
-    if (lane < (uint32_t)(kStUnroll * NT))
-      mw[(size_t)kb * NT + lane] = *reinterpret_cast<const uint64_t*>(stage);
+    for (uint32_t j = lane; j < (uint32_t)S * NT; j += 64u)
+      mw[j] = *reinterpret_cast<const uint64_t*>(stage_w + 8u * j);
   }
 #undef HT_ST_STEP
 #undef HT_ST_TEST
@@ -1316,10 +1331,12 @@ hipError_t launch_peaks_dense(const DevGrid& g, const EvDesc& ev0, const EvDesc*
                               hipStream_t s)
 {
   // one wave per phi cell; two LDS buffers of 16 phi slots of 64 window maxima per theta cell
-  // (none with sectors), then every wave's staging slots for 12 steps of peak words
+  // (none with sectors), then every wave's staging slots for the peak words of its segment's
+  // rows (or of 12 rows when the segment is longer than kStWholeRows)
   const dim3 grid(dense_blocks(g), n_ev), block(64 * g.n_phi);
+  const int slot_rows = g.dense_rows <= kStWholeRows ? g.dense_rows : kStUnroll;
   const size_t lds = (g.phi_sectors ? 0 : 2 * (size_t)g.n_theta * 16 * 256) +
-                     (size_t)g.n_phi * 12 * g.n_theta * 8;
+                     (size_t)g.n_phi * slot_rows * g.n_theta * 8;
 #define HT_ST_CASE(nt_)                                                                        \
   case nt_:                                                                                    \
     if (g.phi_sectors) hipLaunchKernelGGL((k_peak_stencil<nt_, true>), grid, block, lds, s, g, ev0, evs); \
