@@ -117,8 +117,10 @@ typedef struct ht_tuning {
                            this many hits finds its peaks with a stencil over the whole matrix
                            (one read of it, cost independent of the number of candidates)
                            instead of the candidate pool; -1 never. The stencil needs LDS
-                           fill tiles, at most 512 (theta, phi) cells and n_b a multiple of 8;
-                           ht_get_tuning reports -1 where it is unavailable. */
+                           fill tiles, at most 4 theta and 16 phi cells (one wave per phi cell
+                           holds every theta cell's row), and theta cell 0's row and the last
+                           one's less than 2^31 bytes apart; ht_get_tuning reports -1 where it
+                           is unavailable. */
 } ht_tuning;
 
 /* ht_set_tuning: use `tuning` for every later call on grids with these dimensions and ranges
