@@ -123,7 +123,7 @@ def measure_peaks(B, torch, acc_bytes, big_bytes=2 << 30):
     def streams(nbytes):
         buf = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
         buf2 = torch.empty_like(buf)
-        t_wm = [timed(lambda m=m: L.ht_bench_hbm_write(buf.data_ptr(), nbytes, m, sp)) for m in (0, 1, 2)]
+        t_wm = [timed(lambda m=m: L.ht_bench_hbm_write(buf.data_ptr(), nbytes, m, sp)) for m in (0, 1, 2, 3, 4)]
         t_r = timed(lambda: L.ht_bench_hbm_read(buf.data_ptr(), nbytes, sink.data_ptr(), sp))
         t_c = timed(lambda: L.ht_bench_copy(buf2.data_ptr(), buf.data_ptr(), nbytes, sp))
         del buf, buf2
@@ -131,7 +131,9 @@ def measure_peaks(B, torch, acc_bytes, big_bytes=2 << 30):
         return {"write_GBs": round(nbytes / min(t_wm) / 1e9, 1),
                 "write_GBs_by_mode": {"nontemporal16": round(nbytes / t_wm[0] / 1e9, 1),
                                       "store16": round(nbytes / t_wm[1] / 1e9, 1),
-                                      "store4": round(nbytes / t_wm[2] / 1e9, 1)},
+                                      "store4": round(nbytes / t_wm[2] / 1e9, 1),
+                                      "tiles_nontemporal16": round(nbytes / t_wm[3] / 1e9, 1),
+                                      "tiles_store16": round(nbytes / t_wm[4] / 1e9, 1)},
                 "read_GBs": round(nbytes / t_r / 1e9, 1),
                 "copy_GBs": round(2 * nbytes / t_c / 1e9, 1),
                 "buffer_MiB": nbytes >> 20}

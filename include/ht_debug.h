@@ -73,7 +73,9 @@ int ht_profile_read(const char* name, double* total_ms, int64_t* count, int rese
 /* Roofline microbenchmarks: one launch each on `stream` (the caller times it); device buffers.
  * They measure the ceilings the fill and the peak search are compared with.
  * ht_bench_hbm_write: stores over buf[bytes] (bytes a multiple of 16); mode 0: non-temporal
- *   16-byte stores, 1: ordinary 16-byte stores, 2: ordinary 4-byte stores.
+ *   16-byte stores, 1: ordinary 16-byte stores, 2: ordinary 4-byte stores, all three in a
+ *   grid-stride loop; 3 (non-temporal) and 4 (ordinary): 16-byte stores tile by tile, one
+ *   workgroup per 16 KiB tile as the fill writes the matrix (bytes a multiple of 16 KiB).
  * ht_bench_hbm_read: non-temporal 16-byte loads over buf[bytes]; sink: device uint32[1].
  * ht_bench_copy: dst[bytes] = src[bytes]; the reference kernel for hardware byte counters.
  * ht_bench_atomic_rand: n_ops no-return atomicAdd(+1) on 32-bit words at hashed-uniform

@@ -39,6 +39,25 @@ __global__ __launch_bounds__(kBlock) void k_write(u32x4* dst, int64_t n4, uint32
   }
 }
 
+// Stores tile by tile, as the fill writes the matrix: workgroup w writes the 16 KiB tiles w,
+// w + G, ... (G workgroups), each as four 4 KiB rows of 16-byte stores, non-temporal (NT) or
+// ordinary.
+constexpr int64_t kTileVec = 1024;  // 16-byte vectors per 16 KiB tile
+template <bool NT>
+__global__ __launch_bounds__(kBlock) void k_write_tiles(u32x4* dst, int64_t n4, uint32_t value)
+{
+  const u32x4 v = {value, value, value, value};
+  const int64_t n_tiles = n4 / kTileVec;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    u32x4* d = dst + t * kTileVec;
+#pragma unroll
+    for (int k = 0; k < (int)(kTileVec / kBlock); ++k) {
+      if (NT) __builtin_nontemporal_store(v, d + k * kBlock + threadIdx.x);
+      else d[k * kBlock + threadIdx.x] = v;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_read(const u32x4* src, int64_t n4, uint32_t* sink)
 {
   uint32_t acc = 0;
@@ -96,12 +115,19 @@ extern "C" {
 
 int ht_bench_hbm_write(void* buf, int64_t bytes, int32_t mode, void* stream)
 {
-  if (!buf || bytes < 16 || bytes % 16 || mode < 0 || mode > 2) return HT_EINVAL;
+  if (!buf || bytes < 16 || bytes % 16 || mode < 0 || mode > 4) return HT_EINVAL;
+  if (mode >= 3 && bytes % (16 * kTileVec)) return HT_EINVAL;
   const dim3 grid(grid_for(bytes / 16));
   hipStream_t s = (hipStream_t)stream;
   if (mode == 0) hipLaunchKernelGGL(k_write<0>, grid, dim3(kBlock), 0, s, (u32x4*)buf, bytes / 16, 0u);
   else if (mode == 1) hipLaunchKernelGGL(k_write<1>, grid, dim3(kBlock), 0, s, (u32x4*)buf, bytes / 16, 0u);
-  else hipLaunchKernelGGL(k_write<2>, grid, dim3(kBlock), 0, s, (u32x4*)buf, bytes / 16, 0u);
+  else if (mode == 2) hipLaunchKernelGGL(k_write<2>, grid, dim3(kBlock), 0, s, (u32x4*)buf, bytes / 16, 0u);
+  else {
+    // one workgroup per tile, as the fill launches on the paper grid (at most 2^20 of them)
+    const dim3 tgrid((unsigned)std::min<int64_t>(bytes / (16 * kTileVec), 1 << 20));
+    if (mode == 3) hipLaunchKernelGGL(k_write_tiles<true>, tgrid, dim3(kBlock), 0, s, (u32x4*)buf, bytes / 16, 0u);
+    else hipLaunchKernelGGL(k_write_tiles<false>, tgrid, dim3(kBlock), 0, s, (u32x4*)buf, bytes / 16, 0u);
+  }
   return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
 }
 

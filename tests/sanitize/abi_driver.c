@@ -189,6 +189,8 @@ int main(void)
   EXPECT_EINVAL(ht_debug_hit_values(&small, dummy, dummy, dummy, -1, info, dummy, slabs, NULL));
   CHECK(ht_bench_hbm_write(NULL, 16, 0, NULL) == HT_EINVAL);
   CHECK(ht_bench_hbm_write(dummy, 15, 0, NULL) == HT_EINVAL);
+  CHECK(ht_bench_hbm_write(dummy, 16 * 1024 + 16, 3, NULL) == HT_EINVAL);  /* tiles: whole 16 KiB */
+  CHECK(ht_bench_hbm_write(dummy, 16 * 1024, 5, NULL) == HT_EINVAL);
   CHECK(ht_bench_atomic_rand(acc, 0, 1, NULL) == HT_EINVAL);
   CHECK(ht_bench_lds_atomic(0, 1, acc, NULL) == HT_EINVAL);
   printf("abi driver: clean\n");
