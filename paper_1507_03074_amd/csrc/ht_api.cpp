@@ -344,7 +344,7 @@ size_t pool_entries(const DevGrid& g, int64_t n)
 static size_t mask_bytes(const DevGrid& g)
 {
   // one 64-bit word per (slab, row, chunk of kChunkCells columns), rows padded to whole segments
-  // of dense_rows (the stencil's workgroups store their segments whole)
+  // of dense_rows (the stencil's waves store their segments whole)
   const size_t n_chunks = ((size_t)g.n_b + kChunkCells - 1) / kChunkCells;
   const size_t rows = (((size_t)g.n_a + g.dense_rows - 1) / g.dense_rows) * g.dense_rows;
   return 8 * (size_t)g.n_slabs * rows * n_chunks;

@@ -791,22 +791,27 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
   const uint32_t T = g.threshold;
   const uint32_t rows_log2 = (uint32_t)__ffs(g.rows) - 1u;
   const uint32_t gt_log2 = (uint32_t)__ffs(g.group_tiles) - 1u;
-  // Peak words are stored workgroup by workgroup: workgroup lb's region holds S NT words per
-  // phi cell, [phi cell][row of the segment][theta cell], so that each wave writes one
-  // contiguous run. A wave's words wait in its own LDS staging slots, [row][theta cell] after the
-  // W9 buffers: for the whole segment when it has at most kStWholeRows rows (the default), and
-  // go out at the end; else for a block of kStUnroll rows, and go out after each block. Stores
-  // of peak words are slow to complete, and every one is waited for with the loads of the rows
-  // that follow it, so a wave stores as few times as it can.
-  GLOBAL uint64_t* mw = reinterpret_cast<GLOBAL uint64_t*>(gp(e.pk_mask)) +
-                        ((size_t)lb * (size_t)np + (size_t)p) * (size_t)S * NT;
+  // The peak word of (slab sl, row a = seg S + r, chunk c) is at ((sl n_seg + seg) nch + c) S + r:
+  // a wave's words of one theta cell form one contiguous run of S words, and the words of a
+  // group of tiles (rows of one or two slabs) lie close together for the writer. A wave's words
+  // wait in its own LDS staging slots, [row][theta cell] after the W9 buffers: for the whole
+  // segment when it has at most kStWholeRows rows (the default), and go out at the end; else for
+  // a block of kStUnroll rows, and go out after each block. Stores of peak words are slow to
+  // complete, and every one is waited for with the loads of the rows that follow it, so a wave
+  // stores as few times as it can.
+  // (the word's position, computed where the words are stored: kept out of the step loop's
+  // scalar registers)
+#define HT_ST_MW()                                                                             \
+  const uint32_t n_seg_ = ((uint32_t)na + (uint32_t)S - 1u) / (uint32_t)S;                     \
+  GLOBAL uint64_t* const mw = reinterpret_cast<GLOBAL uint64_t*>(gp(e.pk_mask)) +              \
+      (((size_t)p * n_seg_ + (size_t)(lb / (uint32_t)nch)) * (size_t)nch + (size_t)chunk) * (size_t)S; \
+  const uint32_t mt_words = (uint32_t)np * n_seg_ * (uint32_t)nch * (uint32_t)S  /* t to t + 1 */
   constexpr uint32_t kStageStep = NT * 8u;  // bytes per row in a wave's slots
   const bool whole = S <= kStWholeRows;     // uniform
   const uint32_t slot_rows = whole ? (uint32_t)S : (uint32_t)kStUnroll;
   char* const stage_w = reinterpret_cast<char*>(s_w9) + (SECT ? 0u : 2u * kBufBytes) +
                         (uint32_t)p * slot_rows * kStageStep;
-  // slot (row u, t) is at stage_w + 8 (u NT + t): written by lane 0, read back by lane u NT + t
-  char* const stage = stage_w + 8u * lane;
+  // slot (row u, t) is at stage_w + 8 (u NT + t): written by lane 0, read back by the flush
   char* stage_blk = stage_w;  // lane 0's slots of the block's first row
   uint32_t cur_g[NT], cnt[NT];
 #pragma unroll
@@ -941,22 +946,29 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
     if (whole) {  // uniform
       stage_blk += kStUnroll * kStageStep;
     } else {
-      // the block's words leave the staging slots: lane u NT + t stores theta cell t's word of
-      // the block's u-th row (a contiguous run of the wave's region). Lane 0 wrote the slots:
-      // the fence keeps these reads after its writes (with phi sectors no barrier orders them).
+      // the block's words leave the staging slots: lane t kStUnroll + u stores theta cell t's
+      // word of the block's u-th row (runs of kStUnroll words). Lane 0 wrote the slots: the
+      // fence keeps these reads after its writes (with phi sectors no barrier orders them).
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
-      if (lane < (uint32_t)(kStUnroll * NT))
-        mw[(size_t)kb * NT + lane] = *reinterpret_cast<const uint64_t*>(stage);
+      HT_ST_MW();
+      if (lane < (uint32_t)(kStUnroll * NT)) {
+        const uint32_t t = lane / kStUnroll, u = lane - t * kStUnroll;
+        mw[(size_t)t * mt_words + (size_t)kb + u] = *reinterpret_cast<const uint64_t*>(stage_w + 8u * (u * NT + t));
+      }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
     }
   }
-  if (whole) {  // uniform: the segment's words, S NT of them, in runs of 64
+  if (whole) {  // uniform: the segment's words, a run of S per theta cell
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
-    for (uint32_t j = lane; j < (uint32_t)S * NT; j += 64u)
-      mw[j] = *reinterpret_cast<const uint64_t*>(stage_w + 8u * j);
+    HT_ST_MW();
+    for (uint32_t j = lane; j < (uint32_t)S * NT; j += 64u) {
+      const uint32_t t = j / (uint32_t)S, r = j - t * (uint32_t)S;
+      mw[(size_t)t * mt_words + r] = *reinterpret_cast<const uint64_t*>(stage_w + 8u * (r * NT + t));
+    }
   }
 #undef HT_ST_STEP
 #undef HT_ST_TEST
+#undef HT_ST_MW
 #undef HT_ST_R3
 #undef HT_ST_LOAD
 #pragma unroll
@@ -1001,26 +1013,24 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
   const uint32_t nb = (uint32_t)g.n_b, nch = (nb + kChunkCells - 1) / kChunkCells;
   // The group's rows [c_beg / nb, (c_last + L1) / nb) of the slab-major row order, so its words
   // in cell order ("logical" words w = (slab n_a + a) nch + chunk). The stencil stored the word
-  // of (slab (t, p), row a = seg S + r, chunk) at [workgroup seg nch + chunk][p][r][t]; a
-  // thread walks its logical words with that position kept up to date.
+  // of (slab sl, row a = seg S + r, chunk c) at ((sl n_seg + seg) nch + c) S + r; a thread walks
+  // its logical words with that position kept up to date.
   const uint32_t w0 = (c_beg / nb) * nch, w1 = (uint32_t)(((uint64_t)c_last + L1) / nb) * nch;
   const uint32_t per = (w1 - w0 + kBlock - 1) / kBlock;
   const uint32_t lo = min(w1, w0 + per * threadIdx.x), hi = min(w1, lo + per);
   const GLOBAL uint64_t* mw = reinterpret_cast<const GLOBAL uint64_t*>(gp((const uint8_t*)e.pk_mask));
-  const uint32_t na = (uint32_t)g.n_a, np = (uint32_t)g.n_phi, nth = (uint32_t)g.n_theta;
-  const uint32_t S = (uint32_t)g.dense_rows;
+  const uint32_t na = (uint32_t)g.n_a, S = (uint32_t)g.dense_rows;
+  const uint32_t n_seg = (na + S - 1u) / S;
   uint32_t ch = lo % nch, a = (lo / nch) % na, sl = lo / nch / na;
-  uint32_t t = sl / np, pp = sl - t * np, seg = a / S, r = a - seg * S;
+  uint32_t seg = a / S, r = a - seg * S;
   auto rewind = [&]() {
     ch = lo % nch;
     a = (lo / nch) % na;
     sl = lo / nch / na;
-    t = sl / np;
-    pp = sl - t * np;
     seg = a / S;
     r = a - seg * S;
   };
-  auto phys = [&]() { return (((seg * nch + ch) * np + pp) * S + r) * nth + t; };
+  auto phys = [&]() { return ((sl * n_seg + seg) * nch + ch) * S + r; };
   auto next = [&]() {
     if (++ch == nch) {
       ch = 0;
@@ -1032,10 +1042,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
         a = 0;
         seg = 0;
         r = 0;
-        if (++pp == np) {
-          pp = 0;
-          ++t;
-        }
+        ++sl;
       }
     }
   };
