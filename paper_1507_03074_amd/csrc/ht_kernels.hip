@@ -18,6 +18,10 @@
 //                 per group of 16-64 tiles
 //   k_peak_write  per group: its output offset from the earlier groups' totals; the ordered
 //                 peak list
+//   crowded events (at least dense_hits hits) skip the candidate pool: the fill only writes
+//   the matrix, k_peak_stencil tests every cell in one read of it (one wave per phi cell, the
+//   theta cells in its registers, the phi neighbours through LDS) into 64-bit peak words, and
+//   k_peak_write_dense writes the ordered peak list from them
 // ht_peaks on an arbitrary matrix replaces prep and fill with k_cand_scan (one read of it).
 // No kernel synchronises workgroups with each other: on this multi-XCD part an agent-scope
 // release costs an L2 write-back, while a kernel boundary is cheap.
@@ -700,18 +704,20 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
 // DPP wave shifts), then W9(a-1, b) = the maximum of R3 over rows a-2..a (the 3 x 3 (A, B)
 // window), and puts W9 into LDS. After one barrier it reads the W9 of its two phi neighbours,
 // P3 = the maximum of the three phi cells' W9, and tests row a-1: the own slab's parts come from
-// registers, theta cell t - 1 gives P3(t - 1) (before), t + 1 gives P3(t + 1) (after), and each
-// phi neighbour in theta cell t adds 1 when it is a before-neighbour (phi wraps: phi cell 0's
-// left neighbour is the last one, an after-neighbour). With phi sectors there are no phi
-// neighbours, no LDS and no barrier.
+// registers, theta cell t - 1 gives P3(t - 1) (before), t + 1 gives P3(t + 1) (after), and the
+// two phi neighbours in theta cell t join the before- or after-neighbours by their index (phi
+// wraps: phi cell 0's left neighbour is the last one, an after-neighbour; the last one's right
+// neighbour is phi cell 0, a before-neighbour). With phi sectors there are no phi neighbours,
+// no LDS exchange and no barrier.
 //
-// Rows are read with buffer loads, one resource per slab row: a load past the row's n_b cells,
-// or from a row outside the segment's rows a_beg - 1 .. a_end (or outside the matrix), returns
-// zero without touching memory. Each row is loaded kStAhead rows before its step into a ring of
-// kStAhead + 1 register slots; the step loop is unrolled by kStUnroll = lcm(ring slots, 3), so
-// the ring slot, the three rows of R3 history and the three LDS buffers are all fixed registers
-// and offsets. The test of a row is a ballot; its bits 1..62 are the chunk's peak bits, stored as
-// one 64-bit word per (row, chunk) of the peak mask; their count is kept per theta cell in scalar
+// Rows are read with buffer loads, one resource per row spanning that row of every theta cell's
+// slab: a lane whose cell lies outside the row, or a row outside the segment's rows
+// a_beg - 1 .. a_end (or outside the matrix), reads zero without touching memory. Each row is
+// loaded kStAhead rows before its step into a ring of kStAhead + 1 register slots; the step loop
+// is unrolled by kStUnroll, a multiple of the ring slots, of the three rows of R3 history and of
+// the two LDS buffers, so all of them are fixed registers and offsets. The test of a row is a
+// ballot; its bits 1..62 are the chunk's peak bits, one 64-bit peak word per (slab, row, chunk),
+// staged in LDS and stored once per segment; their count is kept per theta cell in scalar
 // registers and added to the row's group of tiles once per group.
 // ---------------------------------------------------------------------------------------------
 constexpr int kStAhead = 3;
