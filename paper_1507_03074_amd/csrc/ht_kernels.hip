@@ -29,6 +29,8 @@
 // Every floating-point step of the bin rule is one binary32 operation, rounded to nearest even,
 // in the documented order: contraction is off for this file, sqrtf and the division are the
 // correctly rounded forms.
+#include <cstdlib>
+
 #include "ht_device.h"
 
 #pragma clang fp contract(off)
@@ -990,7 +992,8 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
 // in B order).
 constexpr int kWriteStage = 4096;  // peaks of a group staged in LDS by the dense writer
 
-__global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc ev0, const EvDesc* evs)
+__global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc ev0, const EvDesc* evs,
+                                                               uint32_t stage_cap)
 {
   __shared__ uint32_t smem[32];
   __shared__ uint32_t s_cells[kWriteStage];
@@ -1091,7 +1094,7 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
       }                                                                                        \
     }                                                                                          \
   } while (0)
-  if (tot <= (uint32_t)kWriteStage) {  // uniform
+  if (tot <= stage_cap) {  // uniform (stage_cap <= kWriteStage)
     uint32_t i = lo_pk;
     if (per <= (uint32_t)kMaxW) {  // uniform
 #pragma unroll
@@ -1363,7 +1366,14 @@ hipError_t launch_peaks_dense(const DevGrid& g, const EvDesc& ev0, const EvDesc*
     default: return hipErrorInvalidValue;  // the tiling offers the stencil for 1-4 theta cells only
   }
 #undef HT_ST_CASE
-  hipLaunchKernelGGL(k_peak_write_dense, dim3(n_groups(g), n_ev), dim3(kBlock), 0, s, g, ev0, evs);
+  // HT_DENSE_STAGE (tests): stage at most that many peaks of a group in LDS, so that smaller
+  // groups take the writer's other path
+  uint32_t stage_cap = kWriteStage;
+  if (const char* v = std::getenv("HT_DENSE_STAGE")) {
+    const long c = std::strtol(v, nullptr, 10);
+    if (c >= 0 && c < kWriteStage) stage_cap = (uint32_t)c;
+  }
+  hipLaunchKernelGGL(k_peak_write_dense, dim3(n_groups(g), n_ev), dim3(kBlock), 0, s, g, ev0, evs, stage_cap);
   return hipGetLastError();
 }
 

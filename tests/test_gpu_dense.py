@@ -44,7 +44,7 @@ def gpu():
 
 @pytest.fixture()
 def env():
-    keys = ("HT_DENSE_HITS", "HT_DENSE_ROWS", "HT_BATCH_GRAPH")
+    keys = ("HT_DENSE_HITS", "HT_DENSE_ROWS", "HT_BATCH_GRAPH", "HT_DENSE_STAGE")
     saved = {k: os.environ.get(k) for k in keys}
     yield os.environ
     for k, v in saved.items():
@@ -162,6 +162,32 @@ def test_dense_peak_counts_per_group_of_tiles(gpu, env, rows, gt):
                 check(B, spec, x, y, z, "%s rows %d groups of %d" % (spec.shape, rows, gt))
         finally:
             B.ht_set_tuning(spec)
+
+
+@pytest.mark.parametrize("stage", [None, "0", "17"], ids=["staged", "unstaged", "mixed"])
+def test_dense_writer_paths(gpu, env, stage):
+    """The ordered writer's paths: a group's peaks staged in LDS (at most HT_DENSE_STAGE of
+    them, else each thread emits its own), and groups of more peak words than a thread holds in
+    registers (groups of 64 tiles of 8 rows: 512 rows of 17 words on the paper grid)."""
+    B = gpu
+    env["HT_DENSE_HITS"] = "1"
+    if stage is not None:
+        env["HT_DENSE_STAGE"] = stage
+    ev = synth.make_event(1, 90)
+    for rows, gt in ((8, 16), (8, 64)):
+        try:
+            B.ht_set_tuning(CFG1, rows=rows, group_tiles=gt)
+            check(B, CFG1, ev.x, ev.y, ev.z, "writer rows %d groups of %d stage %s" % (rows, gt, stage))
+            check(B, CFG1, ev.x, ev.y, ev.z, "truncated", capacity=333)
+        finally:
+            B.ht_set_tuning(CFG1)
+    spec = synth.GridSpec(4, 16, 130, 72, threshold=4)
+    try:
+        B.ht_set_tuning(spec, rows=64, group_tiles=64)
+        x, y, z = random_hits(5, 2000)
+        check(B, spec, x, y, z, "small grid, groups of 64 tiles of 64 rows, stage %s" % stage)
+    finally:
+        B.ht_set_tuning(spec)
 
 
 def test_dense_paper_events_and_truncation(gpu, env):
