@@ -1,13 +1,13 @@
-"""GPU parity of the stencil peak search (crowded events: k_peak_dense over the written matrix, then
-k_peak_write_dense from its peak mask) against the CPU oracle, bit for bit.
+"""GPU parity of the stencil peak search (crowded events: k_peak_stencil over the written matrix,
+then k_peak_write_dense from its peak words) against the CPU oracle, bit for bit.
 
 The fused fill + peak search takes the stencil for events with at least `dense_hits` hits (by
 default 5/16 n_slabs n_b: the 40000-hit served event does) on grids of at most 4 theta and 16 phi
-cells. HT_DENSE_HITS
-moves that threshold, so the same kernels are checked here on small and ragged grids, every row
-segment length (HT_DENSE_ROWS), ragged B chunks, one theta cell, three phi cells (the wrap),
-phi sectors, truncated outputs, pinned-host outputs, batches that mix both searches (graph and
-eager) and the request loop.
+cells. HT_DENSE_HITS moves that threshold, so the same kernels are checked here on small and
+ragged grids, every row segment length (HT_DENSE_ROWS), ragged B chunks, one to four theta
+cells, three to sixteen phi cells (the wrap), phi sectors, both paths of the ordered writer
+(HT_DENSE_STAGE), truncated outputs, pinned-host outputs, batches that mix both searches (graph
+and eager) and the request loop.
 """
 import os
 import sys
