@@ -1003,19 +1003,6 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
   const int t0 = G * g.group_tiles;
   const int nt = min(g.group_tiles, g.n_tiles - t0);
   const bool a8 = ((uintptr_t)e.out & 7u) == 0;
-  uint32_t part = 0;
-  for (int i0 = 0; i0 < G; i0 += 4 * kBlock) {  // uniform
-    uint32_t w[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = i0 + k * kBlock + (int)threadIdx.x;
-      w[k] = i < G ? gp(e.group_pk)[i] : 0u;
-    }
-    part += w[0] + w[1] + w[2] + w[3];
-  }
-  const int64_t base = (int64_t)block_sum(part, smem);
-  if (G == (int)gridDim.x - 1 && threadIdx.x == 0) *gp(e.n_found) = base + gp(e.group_pk)[G];
-  if (base >= e.cap) return;  // uniform
   uint32_t c_beg, L0, c_last, L1;
   tile_range(g, t0, &c_beg, &L0);
   tile_range(g, t0 + nt - 1, &c_last, &L1);
@@ -1065,6 +1052,22 @@ __global__ __launch_bounds__(kBlock) void k_peak_write_dense(DevGrid g, EvDesc e
       wv[k] = k < nw ? mw[phys()] : 0ull;
       next();
     }
+  }
+  // the earlier groups' peak counts give the output offset (loaded while the words arrive)
+  uint32_t part = 0;
+  for (int i0 = 0; i0 < G; i0 += 4 * kBlock) {  // uniform
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * kBlock + (int)threadIdx.x;
+      w[k] = i < G ? gp(e.group_pk)[i] : 0u;
+    }
+    part += w[0] + w[1] + w[2] + w[3];
+  }
+  const int64_t base = (int64_t)block_sum(part, smem);
+  if (G == (int)gridDim.x - 1 && threadIdx.x == 0) *gp(e.n_found) = base + gp(e.group_pk)[G];
+  if (base >= e.cap) return;  // uniform
+  if (per <= (uint32_t)kMaxW) {  // uniform
 #pragma unroll
     for (int k = 0; k < kMaxW; ++k) cnt += (uint32_t)__builtin_popcountll(wv[k]);
   } else {
