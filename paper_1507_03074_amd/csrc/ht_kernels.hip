@@ -1314,7 +1314,8 @@ hipError_t launch_fill(const DevGrid& g, const EvDesc& ev0, const EvDesc* evs, i
   const bool long_lists = max_hits * 3 > (int64_t)2 * kBlock * g.n_slabs;
   // store kind 2: 4-byte stores (the dword path), otherwise 16-byte stores where rows allow
   const bool vec = (g.n_b % 4) == 0 && g.nt_store != 2;
-  const size_t lds = fill_lds_bytes(g);
+  // long lists: 64 spill words past the tile (one per lane) for votes outside the row
+  const size_t lds = fill_lds_bytes(g) + (long_lists ? 64 * sizeof(uint32_t) : 0);
   return launch_fill_nt(g, ev0, evs, n_ev, g.nt_store == 1, vec, emit, long_lists, lds, s);
 }
 
