@@ -719,8 +719,10 @@ __global__ __launch_bounds__(kBlock) void k_peak_write(DevGrid g, EvDesc ev0, co
 // is unrolled by kStUnroll, a multiple of the ring slots, of the three rows of R3 history and of
 // the two LDS buffers, so all of them are fixed registers and offsets. The test of a row is a
 // ballot; its bits 1..62 are the chunk's peak bits, one 64-bit peak word per (slab, row, chunk),
-// staged in LDS and stored once per segment; their count is kept per theta cell in scalar
-// registers and added to the row's group of tiles once per group.
+// staged in LDS and stored once per segment. The words are counted when they are stored, and each
+// wave adds one count per group of tiles its words fall in (a segmented scan over its lanes): a
+// count kept per row in scalar registers cost 35 scalar registers and about a tenth of the
+// kernel's time.
 // ---------------------------------------------------------------------------------------------
 constexpr int kStAhead = 3;
 constexpr int kStSlots = kStAhead + 1;
@@ -742,6 +744,44 @@ __device__ __forceinline__ uint32_t lane_left(uint32_t v)
 __device__ __forceinline__ uint32_t lane_right(uint32_t v)
 {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, true);
+}
+
+// Inclusive maximum over a wave64, with the DPP steps of the inclusive sum (a lane whose source
+// lies outside its row takes the maximum with 0). Every lane of the wave must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_max(uint32_t v)
+{
+  return max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v)
+{
+  v = dpp_max<0x111, 0xf>(v);
+  v = dpp_max<0x112, 0xf>(v);
+  v = dpp_max<0x114, 0xf>(v);
+  v = dpp_max<0x118, 0xf>(v);
+  v = dpp_max<0x142, 0xa>(v);
+  v = dpp_max<0x143, 0xc>(v);
+  return v;
+}
+
+// Adds the peaks of one 64-bit peak word per lane to the peak counts of their groups of tiles.
+// The words a wave holds are in (theta cell, row) order, so the lanes of one group form one run:
+// a scan of the counts and a maximum-scan of the runs' starting sums give each run's total, which
+// its last lane adds with one atomic. A lane with valid false (no word, or a row past the
+// matrix) adds nothing and splits runs. Every lane of the wave must be active.
+__device__ __forceinline__ void add_group_counts(uint32_t* group_pk, bool valid, uint32_t grp, uint64_t word)
+{
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t gv = valid ? grp : 0xffffffffu;  // group numbers are below 2^31
+  const uint32_t c = valid ? (uint32_t)__builtin_popcountll(word) : 0u;
+  const uint32_t incl = wave_incl_scan(c);
+  // the neighbours' groups are read by every lane (no short-circuit: a DPP read of a lane that
+  // is switched off returns 0)
+  const uint32_t gl = lane_left(gv), gr = lane_right(gv);
+  const bool start = (lane == 0u) | (gl != gv);
+  const bool last = (lane == 63u) | (gr != gv);
+  const uint32_t run0 = wave_incl_max(start ? incl - c : 0u);
+  if (valid && last && incl != run0) gatomic_add(group_pk + grp, incl - run0);
 }
 
 // Block b of a grid of G runs on XCD b % 8 (workgroups are dealt to the eight XCDs in turn); the
@@ -821,12 +861,10 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
                         (uint32_t)p * slot_rows * kStageStep;
   // slot (row u, t) is at stage_w + 8 (u NT + t): written by lane 0, read back by the flush
   char* stage_blk = stage_w;  // lane 0's slots of the block's first row
-  uint32_t cur_g[NT], cnt[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    cur_g[t] = ((uint32_t)(t * np + p) * (uint32_t)g.tiles_per_slab + ((uint32_t)a_beg >> rows_log2)) >> gt_log2;
-    cnt[t] = 0u;
-  }
+  // group of tiles of theta cell t's row a (a below n_a)
+  auto group_of = [&](uint32_t t, uint32_t a) {
+    return ((t * (uint32_t)np + (uint32_t)p) * (uint32_t)g.tiles_per_slab + (a >> rows_log2)) >> gt_log2;
+  };
   uint32_t ring[kStSlots][NT], hist[3][NT];
 
   // The next row (rows outside [a_beg - 1, a_end] or the matrix read zeros) into ring slot
@@ -903,18 +941,6 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
     } else {                                                                                   \
       _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) p3_[t_] = wm_[t_] = wq_[t_] = w9_[t_]; \
     }                                                                                          \
-    const int tr_ = a_beg + (kb_) + (kc_) - 2; /* the tested row */                            \
-    if ((tr_ & (g.rows - 1)) == 0) { /* a tile starts here, perhaps a group of tiles */        \
-      _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_) {                                      \
-        const uint32_t gi_ = ((uint32_t)(t_ * np + p) * (uint32_t)g.tiles_per_slab +           \
-                              ((uint32_t)tr_ >> rows_log2)) >> gt_log2;                        \
-        if (gi_ != cur_g[t_]) {                                                                \
-          if (cnt[t_] != 0u && lane == 0u) gatomic_add(e.group_pk + cur_g[t_], cnt[t_]);      \
-          cur_g[t_] = gi_;                                                                     \
-          cnt[t_] = 0u;                                                                        \
-        }                                                                                      \
-      }                                                                                        \
-    }                                                                                          \
     uint64_t pk_[NT];                                                                          \
     if (SECT || p_mid) HT_ST_TEST(0);                                                          \
     else if (p == 0) HT_ST_TEST(1);                                                            \
@@ -922,10 +948,6 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
     if (lane == 0u) { /* lane 0 puts the words into the wave's staging slots */               \
       _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                        \
         *reinterpret_cast<uint64_t*>(stage_blk + ((kc_) - 2) * kStageStep + 8 * t_) = pk_[t_]; \
-    }                                                                                          \
-    if (tr_ < na) { /* rows past the matrix (the last segment's) are zeros, not counted */    \
-      _Pragma("unroll") for (int t_ = 0; t_ < NT; ++t_)                                        \
-        cnt[t_] += (uint32_t)__builtin_popcountll(pk_[t_]);                                    \
     }                                                                                          \
     HT_ST_LOAD(vs_);                                                                           \
   } while (0)
@@ -959,19 +981,27 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
       // fence keeps these reads after its writes (with phi sectors no barrier orders them).
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
       HT_ST_MW();
-      if (lane < (uint32_t)(kStUnroll * NT)) {
-        const uint32_t t = lane / kStUnroll, u = lane - t * kStUnroll;
-        mw[(size_t)t * mt_words + (size_t)kb + u] = *reinterpret_cast<const uint64_t*>(stage_w + 8u * (u * NT + t));
-      }
+      const bool in = lane < (uint32_t)(kStUnroll * NT);
+      const uint32_t t = in ? lane / kStUnroll : 0u, u = in ? lane - t * kStUnroll : 0u;
+      const uint64_t w = *reinterpret_cast<const uint64_t*>(stage_w + 8u * (u * NT + t));
+      if (in) mw[(size_t)t * mt_words + (size_t)kb + u] = w;
+      const uint32_t a = (uint32_t)(a_beg + kb) + u;
+      add_group_counts(e.group_pk, in && a < (uint32_t)na, group_of(t, a), w);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
     }
   }
   if (whole) {  // uniform: the segment's words, a run of S per theta cell
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
     HT_ST_MW();
-    for (uint32_t j = lane; j < (uint32_t)S * NT; j += 64u) {
-      const uint32_t t = j / (uint32_t)S, r = j - t * (uint32_t)S;
-      mw[(size_t)t * mt_words + r] = *reinterpret_cast<const uint64_t*>(stage_w + 8u * (r * NT + t));
+    const uint32_t n_w = (uint32_t)S * NT;
+    for (uint32_t j0 = 0; j0 < n_w; j0 += 64u) {  // uniform: every lane counts
+      const uint32_t j = j0 + lane;
+      const bool in = j < n_w;
+      const uint32_t t = in ? j / (uint32_t)S : 0u, r = in ? j - t * (uint32_t)S : 0u;
+      const uint64_t w = *reinterpret_cast<const uint64_t*>(stage_w + 8u * (r * NT + t));
+      if (in) mw[(size_t)t * mt_words + r] = w;
+      const uint32_t a = (uint32_t)a_beg + r;
+      add_group_counts(e.group_pk, in && a < (uint32_t)na, group_of(t, a), w);
     }
   }
 #undef HT_ST_STEP
@@ -979,9 +1009,6 @@ __global__ __launch_bounds__(1024) void k_peak_stencil(DevGrid g, EvDesc ev0, co
 #undef HT_ST_MW
 #undef HT_ST_R3
 #undef HT_ST_LOAD
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-    if (cnt[t] != 0u && lane == 0u) gatomic_add(e.group_pk + cur_g[t], cnt[t]);
 }
 
 // Ordered output of a dense event: one workgroup per group of tiles (a contiguous range of rows
