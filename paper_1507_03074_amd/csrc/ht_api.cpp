@@ -199,11 +199,11 @@ Tiling choose_tiling(const ht_grid& g)
     if (forced > 0) s_rows = std::min(forced, 4096);
     t.dense_rows = std::max(12, ((s_rows + 11) / 12) * 12);
   }
-  // default: events with at least 5/16 n_slabs n_b hits, about 0.3 hits per (theta, phi, B)
+  // default: events with at least n_slabs n_b / 4 hits, a quarter of a hit per (theta, phi, B)
   // cell, where the stencil's one pass over the matrix measured faster than the candidate pool
-  // (on the 4x16x1024x1024 grid: 20480 hits; the pool won up to 18k hits, the stencil from 22k);
+  // (on the 4x16x1024x1024 grid: 16384 hits; the pool won up to 15k hits, the stencil from 18k);
   // -1 never
-  int64_t dh = ((int64_t)g.n_theta * g.n_phi * g.n_b * 5 + 15) / 16;
+  int64_t dh = ((int64_t)g.n_theta * g.n_phi * g.n_b + 3) / 4;
   const int forced_dh = env_int("HT_DENSE_HITS", 0);
   if (forced_dh != 0) dh = forced_dh;
   if (have && tu.dense_hits != 0) dh = tu.dense_hits;

@@ -132,7 +132,7 @@ def test_tuning_validated_and_applied_on_host(lib):
             B.ht_set_tuning(spec, **bad)
         assert B.ht_get_tuning(spec).as_dict() == default
     assert default["tiles_per_block"] >= 1 and default["nt_store"] in (0, 1, 2)
-    assert default["dense_hits"] == 5 * 4 * 16 * 1024 // 16
+    assert default["dense_hits"] == 4 * 16 * 1024 // 4
     B.ht_set_tuning(spec, rows=4, group_tiles=32, cand_cap=128, nt_store=2, tiles_per_block=16,
                     dense_hits=20000)
     try:

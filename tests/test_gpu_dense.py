@@ -2,7 +2,7 @@
 then k_peak_write_dense from its peak words) against the CPU oracle, bit for bit.
 
 The fused fill + peak search takes the stencil for events with at least `dense_hits` hits (by
-default 5/16 n_slabs n_b: the 40000-hit served event does) on grids of at most 4 theta and 16 phi
+default n_slabs n_b / 4: the 40000-hit served event does) on grids of at most 4 theta and 16 phi
 cells. HT_DENSE_HITS moves that threshold, so the same kernels are checked here on small and
 ragged grids, every row segment length (HT_DENSE_ROWS), ragged B chunks, one to four theta
 cells, three to sixteen phi cells (the wrap), phi sectors, both paths of the ordered writer
@@ -89,7 +89,7 @@ def random_hits(seed, n, spread=1000.0):
 def test_dense_threshold_reported(gpu):
     B = gpu
     t = B.ht_get_tuning(CFG1)
-    assert t.dense_hits == 5 * 4 * 16 * 1024 // 16
+    assert t.dense_hits == 4 * 16 * 1024 // 4
     assert B.ht_get_tuning(synth.GridSpec(4, 16, 64, 60)).dense_hits > 0
     # a wave per phi cell holds every theta cell: at most 16 phi and 4 theta cells
     assert B.ht_get_tuning(synth.WORKLOADS[4].grid).dense_hits == -1
