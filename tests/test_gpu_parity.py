@@ -322,6 +322,33 @@ def test_empty_and_degenerate_events(gpu):
     assert gn == 0 and np.array_equal(gM, M)
 
 
+@pytest.mark.parametrize("n_hits", [40, 900])
+@pytest.mark.parametrize("rows", [0, 4, 8])
+def test_bin_edges_bit_exact(gpu, n_hits, rows):
+    """Votes exactly on the B range's edges: B = 0 (as -0 for y < 0: still in bin 0) and B = b_max
+    (outside the half-open range), with A-bin centres on integers, through the short-list fill
+    (40 hits) and the branch-free long-list fill (900 hits: more than two records per thread and
+    slab), with a short last tile (10 A rows in tiles of 4 or 8)."""
+    B = gpu
+    spec = synth.GridSpec(1, 4, 10, 16, a_min=0.0, a_max=20.0, b_min=0.0, b_max=16.0, threshold=3)
+    say("bin edges", n_hits, rows)
+    rng = np.random.default_rng(7 + n_hits + rows)
+    edge = np.array([(8.0, -4.0), (8.0, 4.0), (0.0, 32.0), (0.0, 31.5), (0.0, -2.0)], np.float32)
+    pick = rng.integers(0, len(edge), n_hits // 2)
+    x = np.concatenate([edge[pick, 0], rng.uniform(-20.0, 20.0, n_hits - pick.size)]).astype(np.float32)
+    y = np.concatenate([edge[pick, 1], rng.uniform(-20.0, 20.0, n_hits - pick.size)]).astype(np.float32)
+    z = rng.uniform(-5.0, 5.0, n_hits).astype(np.float32)
+    if rows:
+        B.ht_set_tuning(spec, rows=rows)
+    try:
+        gM, gc, gv, gn = gpu_fused(B, spec, x, y, z)
+    finally:
+        B.ht_set_tuning(spec)
+    M, votes, oc, ov, on = oracle_run(spec, x, y, z)
+    assert int(M[0, :, 2, 0].sum()) >= 2  # the B = 0 votes are there
+    assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "edges %d %d" % (n_hits, rows))
+
+
 def test_batch_matches_single_events(gpu):
     B = gpu
     hits, specs = [], CFG0

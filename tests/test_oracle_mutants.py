@@ -44,6 +44,8 @@ MUTANTS = [
      "phi_cs[2 * m] = (float)sin(ang);\n    phi_cs[2 * m + 1] = (float)cos(ang);"),
     ("last B bin dropped", "if (!(f >= 0.0f && f < nb_f)) continue;",
      "if (!(f >= 0.0f && f < nb_f - 1.0f)) continue;"),
+    ("lower B edge open", "if (!(f >= 0.0f && f < nb_f)) continue;",
+     "if (!(f > 0.0f && f < nb_f)) continue;"),
     ("A index reversed in the scatter", "M[(slab * n_a + i) * n_b + j] += 1u;",
      "M[(slab * n_a + (n_a - 1 - i)) * n_b + j] += 1u;"),
     ("theta boundary loop off by one", "for (int32_t m = 1; m < 2 * g->n_theta; ++m)\n    s_th",

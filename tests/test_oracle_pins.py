@@ -288,6 +288,41 @@ def test_hand_worked_examples(oracle_mod):
         assert [[int(c), int(v)] for c, v in zip(cells, vv)] == case["peaks"], case["name"]
 
 
+# Exact bin edges. On a grid with A-bin centres A2/2 = 1, 3, 5, ... (A2 = 2, 6, 10, ...) and B in
+# [0, 16) with 1 mm bins, the circle of hit (x, y) gives B = (x^2 + y^2 - A2 x) / (2 y) exactly:
+# - (8, -4) and (8, 4): x^2 + y^2 = 80 = A2 x on A row 2, so B = 0 there, the lower edge of bin 0
+#   (in binary32 the product (80 - 80) / (2 y) is -0 for y < 0, which is still >= 0);
+# - (0, 32): B = 16 on every row, the upper edge of the range, which is open: no vote;
+# - (0, 31.5): B = 15.75 on every row, bin 15;
+# - (0, -2): B = -1 on every row, below the range: no vote.
+EDGE_GRID = synth.GridSpec(1, 4, 8, 16, a_min=0.0, a_max=16.0, b_min=0.0, b_max=16.0, threshold=3)
+
+
+@pytest.mark.pin
+def test_bin_edges_exact(oracle_mod):
+    g = og(oracle_mod, EDGE_GRID)
+    for (x, y), rows in [((8.0, -4.0), {2: 0}), ((8.0, 4.0), {2: 0}), ((0.0, 32.0), {}),
+                         ((0.0, 31.5), {a: 15 for a in range(8)}), ((0.0, -2.0), {})]:
+        M, _ = oracle_mod.fill(g, np.array([x], np.float32), np.array([y], np.float32),
+                               np.array([1.0], np.float32))
+        for a, b in rows.items():
+            # the hit lies in two phi cells (half-bin widening) and the one theta cell
+            assert int(M[0, :, a, b].sum()) == 2, ((x, y), a, b)
+        if not rows:
+            assert not M.any(), (x, y)
+        # the B bin on every other row follows from the exact circle
+        for a in range(8):
+            if a in rows:
+                continue
+            A2 = 4.0 * a + 2.0
+            Bx = Fraction(int(x * 2), 2) ** 2 + Fraction(int(y * 2), 2) ** 2 - Fraction(int(A2)) * Fraction(int(x * 2), 2)
+            Bx /= 2 * Fraction(int(y * 2), 2)
+            expect = int(math.floor(Bx)) if 0 <= Bx < 16 else None
+            got = np.argwhere(M[0, :, a, :].sum(axis=0))
+            assert (expect is None and got.size == 0) or (got.size == 1 and int(got[0, 0]) == expect), \
+                ((x, y), a, expect, got)
+
+
 # ---------------------------------------------------------------------------------------------
 # Invariants of the vote matrix
 # ---------------------------------------------------------------------------------------------
