@@ -267,16 +267,28 @@ def test_candidate_overflow_uses_dense_path(gpu, env_tiling):
         B.ht_set_tuning(CFG0)
 
 
-def test_paper_sized_events_bit_exact(gpu):
-    """The 4x16x1024x1024 workload (5000 hits) in the configuration the benchmark times."""
+# the launch shape bench.py pins for its main line (rows 4, groups of 16 tiles, the default pool
+# entries per tile, non-temporal stores, one tile per workgroup)
+BENCH_SHAPE = dict(rows=4, group_tiles=16, cand_cap=0, nt_store=1, tiles_per_block=1)
+
+
+@pytest.mark.parametrize("shape", ["default", "bench"])
+def test_paper_sized_events_bit_exact(gpu, shape):
+    """The 4x16x1024x1024 workload (5000 hits) at the library's default shape and at the shape
+    the benchmark times."""
     B = gpu
-    for e in (0, 1, 2):
-        say("workload 1 event", e)
-        ev = synth.make_event(1, e)
-        gM, gc, gv, gn = gpu_fused(B, CFG1, ev.x, ev.y, ev.z)
-        M, votes, oc, ov, on = oracle_run(CFG1, ev.x, ev.y, ev.z)
-        assert_same(CFG1, gM, gc, gv, gn, M, oc, ov, on, "event %d" % e)
-        assert on > 100
+    if shape == "bench":
+        B.ht_set_tuning(CFG1, **BENCH_SHAPE)
+    try:
+        for e in (0, 1, 2):
+            say("workload 1 event", e, shape)
+            ev = synth.make_event(1, e)
+            gM, gc, gv, gn = gpu_fused(B, CFG1, ev.x, ev.y, ev.z)
+            M, votes, oc, ov, on = oracle_run(CFG1, ev.x, ev.y, ev.z)
+            assert_same(CFG1, gM, gc, gv, gn, M, oc, ov, on, "event %d %s" % (e, shape))
+            assert on > 100
+    finally:
+        B.ht_set_tuning(CFG1)
 
 
 def test_empty_and_degenerate_events(gpu):
