@@ -361,6 +361,40 @@ def test_bin_edges_bit_exact(gpu, n_hits, rows):
     assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "edges %d %d" % (n_hits, rows))
 
 
+def boundary_hits(n_theta, n_phi, seed):
+    """Hits on and next to the sector boundaries: azimuths m pi / n_phi and polar angles
+    m pi / (2 n_theta) (the edges of the half-widened cells), each direction also one float32 step
+    either side in x, y and z, at several radii."""
+    rng = np.random.default_rng(seed)
+    xs, ys, zs = [], [], []
+    for m in range(2 * n_phi):
+        ph = m * np.pi / n_phi
+        for mt in range(1, 2 * n_theta):
+            th = mt * np.pi / (2 * n_theta)
+            for r in rng.uniform(30.0, 1000.0, 2):
+                x, y = np.float32(r * np.cos(ph)), np.float32(r * np.sin(ph))
+                z = np.float32(r / np.tan(th)) if abs(np.tan(th)) > 1e-12 else np.float32(0.0)
+                for dx, dy, dz in ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                    xs.append(np.nextafter(x, np.float32(np.inf * dx)) if dx else x)
+                    ys.append(np.nextafter(y, np.float32(np.inf * dy)) if dy else y)
+                    zs.append(np.nextafter(z, np.float32(np.inf * dz)) if dz else z)
+    return (np.array(xs, np.float32), np.array(ys, np.float32), np.array(zs, np.float32))
+
+
+@pytest.mark.parametrize("spec", [CFG0, synth.GridSpec(3, 5, 64, 64, threshold=3),
+                                  synth.GridSpec(2, 4, 48, 40, threshold=2, phi_sectors=True)])
+def test_sector_boundaries_bit_exact(gpu, spec):
+    """Hits exactly on, and one float32 step off, every theta and phi boundary direction: the
+    half-plane tests of the preparation against the oracle's, through the whole fused call."""
+    B = gpu
+    x, y, z = boundary_hits(spec.n_theta, spec.n_phi, 11)
+    say("sector boundaries", spec.shape, x.size)
+    gM, gc, gv, gn = gpu_fused(B, spec, x, y, z)
+    M, votes, oc, ov, on = oracle_run(spec, x, y, z)
+    assert votes > 0
+    assert_same(spec, gM, gc, gv, gn, M, oc, ov, on, "boundaries %s" % (spec.shape,))
+
+
 def test_batch_matches_single_events(gpu):
     B = gpu
     hits, specs = [], CFG0
