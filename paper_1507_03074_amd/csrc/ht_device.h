@@ -260,7 +260,11 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
     tile_quarter<VEC>(L, wave, &q0, &q1);
     // candidates of the earlier quarters
     uint32_t run = base + (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
-    const uint64_t below = (1ull << lane) - 1ull;
+    // a lane's rank among the ballot's set lanes below it: mbcnt adds the count of set bits below
+    // the lane in one half of the mask to its second operand
+    auto rank = [](uint64_t m, uint32_t base) {
+      return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
+    };
     if (VEC) {
       const u32x4* s4 = reinterpret_cast<const u32x4*>(s_tile);
       const u32x4 zero4 = {0u, 0u, 0u, 0u};
@@ -277,8 +281,7 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
           const uint32_t c = cell0 + 4u * (b + (uint32_t)(k * 64 + lane));
           const bool c0 = v[k].x >= T, c1 = v[k].y >= T, c2 = v[k].z >= T, c3 = v[k].w >= T;
           const uint64_t m0 = __ballot(c0), m1 = __ballot(c1), m2 = __ballot(c2), m3 = __ballot(c3);
-          uint32_t r = run + (uint32_t)(__popcll(m0 & below) + __popcll(m1 & below) +
-                                        __popcll(m2 & below) + __popcll(m3 & below));
+          uint32_t r = rank(m3, rank(m2, rank(m1, rank(m0, run))));
           if (c0) st_cand(e.pool, r++, c, v[k].x);
           if (c1) st_cand(e.pool, r++, c + 1u, v[k].y);
           if (c2) st_cand(e.pool, r++, c + 2u, v[k].z);
@@ -292,7 +295,7 @@ __device__ void emit_candidates(const DevGrid& g, const EvDesc& e, int tile, uin
         const uint32_t v = i < q1 ? s_tile[i] : 0u;
         const bool c = v >= T;
         const uint64_t m = __ballot(c);
-        if (c) st_cand(e.pool, run + (uint32_t)__popcll(m & below), cell0 + i, v);
+        if (c) st_cand(e.pool, rank(m, run), cell0 + i, v);
         run += (uint32_t)__popcll(m);
       }
     }
