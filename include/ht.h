@@ -116,7 +116,9 @@ typedef struct ht_tuning {
   int32_t dense_hits;   /* crowded events: a fused fill + peak search of an event with at least
                            this many hits finds its peaks with a stencil over the whole matrix
                            (one read of it, cost independent of the number of candidates)
-                           instead of the candidate pool; -1 never. The stencil needs LDS
+                           instead of the candidate pool; -1 never. The default is
+                           n_theta n_phi n_b / 4 hits (16384 on the 4x16x1024x1024 grid), about
+                           where the stencil starts to beat the pool. The stencil needs LDS
                            fill tiles, at most 4 theta and 16 phi cells (one wave per phi cell
                            holds every theta cell's row), and theta cell 0's row and the last
                            one's less than 2^31 bytes apart; ht_get_tuning reports -1 where it
